@@ -1,0 +1,187 @@
+/*
+ * spmm.h -- C ABI of the MI355X semi-external SpMM library (libspmm.so).
+ *
+ * Computes Y = A X for a sparse n_rows x n_cols matrix A (typically the
+ * adjacency matrix of a power-law graph) and a dense n_cols x k matrix X,
+ * k = 1..64.  This is the operation SparseMatrixMultiply(spm, inM) -> outM of
+ * Algorithm 1 of Zheng et al., "Semi-External Memory Sparse Matrix
+ * Multiplication for Billion-Node Graphs": the output starts at zero and
+ * every non-zero (r, c, v) of A adds v * X[c, :] to Y[r, :].  SpMV is k = 1.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: SPMM_OK (0) or a negative spmm_status_t.  No exception
+ *     crosses the ABI.  spmm_last_error() returns a thread-local message
+ *     describing the most recent failure on the calling thread.
+ *   - Host pointers are read during the call only and stay owned by the
+ *     caller.  Device pointers (X, Y, scales, vectors) are owned by the
+ *     caller; the library never frees them.
+ *   - Dense matrices are row-major: element (i, j) of X is at
+ *     X[i * ldx + j] with ldx >= k; likewise for Y with ldy.
+ *   - Device-side entry points are asynchronous on the stream they are given
+ *     and return as soon as the work is enqueued, except where noted.
+ *   - A handle may be used from one stream at a time.  Calls on the same
+ *     handle from different host threads must be serialised by the caller.
+ *   - On failure, no output other than Y (then undefined) is modified.
+ */
+#ifndef SPMM_H
+#define SPMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPMM_OK = 0,
+    SPMM_EINVAL = -1,        /* bad argument or malformed CSR                 */
+    SPMM_ENOMEM = -2,        /* host or device allocation failed              */
+    SPMM_EHIP = -3,          /* a HIP runtime call failed                     */
+    SPMM_EUNSUPPORTED = -4,  /* valid request this build does not support     */
+    SPMM_ESTATE = -5         /* handle is in the wrong state for this call    */
+} spmm_status_t;
+
+/* Element type of X.  Accumulation is always FP32 and Y is always FP32. */
+typedef enum {
+    SPMM_X_F32 = 0,
+    SPMM_X_BF16 = 1,       /* round-to-nearest-even of the FP32 value          */
+    SPMM_X_FP8_E4M3 = 2    /* OCP E4M3 of X[i][j] * s_j, per-column scale s_j  */
+} spmm_xdtype_t;
+
+/*
+ * Kernel variant of a tile.  A tile is the block of A formed by h
+ * consecutive rows (a tile row, "slab") and w consecutive columns, with
+ * 16-bit row and column indices local to the tile (Section 3.2).  Every
+ * variant computes the same product; they differ in how the tile's entries
+ * are encoded and mapped onto the 64 lanes of a wavefront:
+ *   COO    - every entry as a (row, col) pair, one lane (group) per entry.
+ *   ROW    - rows with one entry as COO pairs, the other rows in the
+ *            paper's SCSR+COO layout (Section 3.2): one lane (group) per row.
+ *   HYBRID - as ROW, but rows of 64 or more entries are given a whole
+ *            wavefront, which splits the row and reduces it with shuffles.
+ *   WAVE   - single-entry rows as COO, every other row one wavefront.
+ */
+typedef enum {
+    SPMM_VAR_COO = 0,
+    SPMM_VAR_ROW = 1,
+    SPMM_VAR_HYBRID = 2,
+    SPMM_VAR_WAVE = 3
+} spmm_variant_t;
+#define SPMM_NUM_VARIANTS 4
+
+/* Number of per-tile features reported by spmm_tile_features. */
+#define SPMM_NUM_FEATURES 8
+
+/* Where the encoded tiles live. */
+typedef enum {
+    SPMM_PLACE_DEVICE = 0,       /* HBM; used by spmm_run                     */
+    SPMM_PLACE_PINNED_HOST = 1   /* pinned host DRAM; used by spmm_stream_run */
+} spmm_place_t;
+
+/* Build options.  A zero-initialised struct selects every default. */
+typedef struct {
+    uint32_t tile_rows;      /* h: rows per tile row; 0 -> 256; 1..4096          */
+    uint32_t tile_cols;      /* w: columns per tile; 0 -> 65536; power of 2,
+                                 <= 65536 (16-bit local column index)           */
+    int32_t fixed_variant;   /* variant of every tile; < 0 -> SPMM_VAR_HYBRID    */
+    uint32_t item_nnz;       /* target non-zeros per work item (one wavefront);
+                                 tile rows above it are split; 0 -> 16384         */
+    uint32_t place;          /* spmm_place_t                                     */
+    uint32_t threads;        /* host threads for the build; 0 -> all cores       */
+    uint32_t validate;       /* 1 -> reject unsorted/duplicate/out-of-range CSR  */
+    uint32_t max_kc;         /* widest block of X columns one kernel launch
+                                 accumulates: 16 or 32; 0 -> 16                   */
+} spmm_build_opts;
+
+typedef struct spmm_handle_s* spmm_handle_t;
+
+/*
+ * Convert a CSR matrix into the tile store (the CSR -> SCSR conversion of
+ * Section 6, Table 3).  Host work only: the device copy is made by the
+ * first spmm_run (or the pinned host copy by the first spmm_stream_run).
+ *   n_rows, n_cols : matrix shape, 0 <= n <= 2^31 - 1.
+ *   row_ptr        : host int64[n_rows + 1], row_ptr[0] = 0, non-decreasing.
+ *   col_idx        : host int32[row_ptr[n_rows]], columns of each row sorted
+ *                    ascending without duplicates (checked if opts->validate).
+ *   values         : host float[nnz] or NULL for a binary (all-ones) A.
+ *   opts           : NULL for defaults.
+ *   out            : receives the handle, set only on SPMM_OK.
+ * The CSR arrays are copied; the caller may free them after the call.
+ * Errors: SPMM_EINVAL (bad shape/options/CSR), SPMM_ENOMEM, SPMM_EHIP.
+ */
+spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr,
+                               const int32_t* col_idx, const float* values,
+                               const spmm_build_opts* opts, spmm_handle_t* out);
+
+/* Release a handle and everything it owns.  NULL is ignored.  Waits for
+   work already enqueued on the handle's device buffers to finish. */
+void spmm_destroy(spmm_handle_t h);
+
+/* Message for the last failure on this thread ("" if none).  The pointer
+   stays valid until the next library call on this thread. */
+const char* spmm_last_error(void);
+
+/*
+ * Y = A X on the device (A placed in HBM).
+ *   X     : device pointer, n_cols x k, element type dt, row stride ldx >= k
+ *           (elements).  FP32 rows 16-byte aligned run fastest.
+ *   k     : 1..64.
+ *   col_scale : device float[k], the FP8 column scales s_j (Y is divided by
+ *           s_j at write-out); must be NULL unless dt is SPMM_X_FP8_E4M3.
+ *   Y     : device pointer, n_rows x k FP32, row stride ldy >= k; every
+ *           element of the n_rows x k block is overwritten.
+ *   s     : HIP stream (0 = null stream).
+ * The first call on a handle copies the tile payload to HBM and allocates
+ * the partial-result buffer of split tile rows (synchronous allocations).
+ * Errors: SPMM_EINVAL (bad k/ld/pointer/dtype), SPMM_ESTATE (tiles placed in
+ * host memory), SPMM_ENOMEM, SPMM_EHIP.
+ */
+spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
+                       const float* col_scale, float* Y, int64_t ldy, hipStream_t s);
+
+/*
+ * Rebuild the CSR of A from the encoded work items (host copy of the tile
+ * payload), walking them with the same indexing as the kernels.  A check of
+ * the encoding: the result equals the CSR given to spmm_build_tiles.
+ *   row_ptr : host int64[n_rows + 1] (output);  col_idx : host int32[nnz];
+ *   values  : host float[nnz] for a weighted A, else NULL.
+ * Errors: SPMM_EINVAL (NULL arguments, values for a binary A), SPMM_ENOMEM.
+ */
+spmm_status_t spmm_decode_tiles(spmm_handle_t h, int64_t* row_ptr, int32_t* col_idx, float* values);
+
+/* Shape and storage statistics of a handle. */
+typedef struct {
+    uint64_t n_rows, n_cols, nnz;
+    uint64_t tile_rows, tile_cols;
+    uint64_t n_slabs;          /* tile rows                                      */
+    uint64_t n_tiles;          /* non-empty tiles                                */
+    uint64_t sum_nnr;          /* sum over tiles of non-empty rows               */
+    uint64_t sum_nnc;          /* sum over tiles of non-empty columns            */
+    uint64_t n_items;          /* work items (one wavefront each)                */
+    uint64_t n_parts;          /* items whose tile row is split across items     */
+    uint64_t blob_bytes;       /* encoded tile payload                           */
+    uint64_t desc_bytes;       /* work-item descriptors and combine lists        */
+    uint64_t variant_tiles[SPMM_NUM_VARIANTS];
+    uint64_t variant_nnz[SPMM_NUM_VARIANTS];
+} spmm_stats_t;
+
+spmm_status_t spmm_get_stats(spmm_handle_t h, spmm_stats_t* out);
+
+/*
+ * Byte model of the paper's tile format for t x t tiles (Section 3.2), read
+ * straight from a CSR (same argument rules as spmm_build_tiles):
+ *   n_tiles = non-empty tiles, sum_nnr / sum_nnc = non-empty rows / columns
+ *   summed over tiles.  S_SCSR of the matrix is 2 sum_nnr + (2 + c) nnz.
+ */
+spmm_status_t spmm_model_tiles(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr,
+                               const int32_t* col_idx, int64_t t, uint64_t* n_tiles,
+                               uint64_t* sum_nnr, uint64_t* sum_nnc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMM_H */

@@ -1,0 +1,236 @@
+"""Python binding of libspmm.so (the C ABI declared in include/spmm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch tensors are accepted for device memory and
+streams (their data pointers and stream handles are passed through); raw
+integer device pointers work as well.  If the library has not been built,
+importing the functions raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmm.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "spmm.h")
+
+# spmm_status_t
+SPMM_OK, SPMM_EINVAL, SPMM_ENOMEM, SPMM_EHIP, SPMM_EUNSUPPORTED, SPMM_ESTATE = 0, -1, -2, -3, -4, -5
+# spmm_xdtype_t
+SPMM_X_F32, SPMM_X_BF16, SPMM_X_FP8_E4M3 = 0, 1, 2
+# spmm_variant_t
+SPMM_VAR_COO, SPMM_VAR_ROW, SPMM_VAR_HYBRID, SPMM_VAR_WAVE = 0, 1, 2, 3
+SPMM_NUM_VARIANTS = 4
+SPMM_NUM_FEATURES = 8
+VARIANT_NAMES = ("coo", "row", "hybrid", "wave")
+# spmm_place_t
+SPMM_PLACE_DEVICE, SPMM_PLACE_PINNED_HOST = 0, 1
+
+_STATUS_NAMES = {0: "SPMM_OK", -1: "SPMM_EINVAL", -2: "SPMM_ENOMEM", -3: "SPMM_EHIP",
+                 -4: "SPMM_EUNSUPPORTED", -5: "SPMM_ESTATE"}
+
+
+class SpmmError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func} -> {_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class spmm_build_opts(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_uint32), ("tile_cols", ctypes.c_uint32),
+                ("fixed_variant", ctypes.c_int32), ("item_nnz", ctypes.c_uint32),
+                ("place", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("validate", ctypes.c_uint32), ("max_kc", ctypes.c_uint32)]
+
+
+class spmm_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "n_rows", "n_cols", "nnz", "tile_rows", "tile_cols", "n_slabs", "n_tiles", "sum_nnr",
+        "sum_nnc", "n_items", "n_parts", "blob_bytes", "desc_bytes")] + [
+        ("variant_tiles", ctypes.c_uint64 * SPMM_NUM_VARIANTS),
+        ("variant_nnz", ctypes.c_uint64 * SPMM_NUM_VARIANTS)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libspmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, vp, u64p = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)
+    L.spmm_last_error.restype = ctypes.c_char_p
+    L.spmm_last_error.argtypes = []
+    L.spmm_build_tiles.restype = i32
+    L.spmm_build_tiles.argtypes = [i64, i64, vp, vp, vp, ctypes.POINTER(spmm_build_opts),
+                                   ctypes.POINTER(vp)]
+    L.spmm_destroy.restype = None
+    L.spmm_destroy.argtypes = [vp]
+    L.spmm_run.restype = i32
+    L.spmm_run.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp]
+    L.spmm_get_stats.restype = i32
+    L.spmm_get_stats.argtypes = [vp, ctypes.POINTER(spmm_stats_t)]
+    L.spmm_decode_tiles.restype = i32
+    L.spmm_decode_tiles.argtypes = [vp, vp, vp, vp]
+    L.spmm_model_tiles.restype = i32
+    L.spmm_model_tiles.argtypes = [i64, i64, vp, vp, i64, u64p, u64p, u64p]
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of every function declared in include/spmm.h."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spmm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def spmm_last_error() -> str:
+    return load_library().spmm_last_error().decode()
+
+
+def _check(st: int, func: str):
+    if st != SPMM_OK:
+        raise SpmmError(st, func, spmm_last_error())
+
+
+def _host(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(x):
+    """Device/host pointer of a torch tensor, numpy array, int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+def _stream(stream, like=None):
+    if stream is None:
+        if like is not None and hasattr(like, "device") and getattr(like, "is_cuda", False):
+            import torch
+            return torch.cuda.current_stream(like.device).cuda_stream
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Handle:
+    """Owns an spmm_handle_t; destroyed on close() or garbage collection."""
+
+    def __init__(self, ptr: int, n_rows: int, n_cols: int):
+        self.ptr = ptr
+        self.n_rows = n_rows
+        self.n_cols = n_cols
+
+    def close(self):
+        if self.ptr:
+            spmm_destroy(self)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        return ctypes.c_void_p(self.ptr)
+
+
+def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *,
+                     tile_rows: int = 0, tile_cols: int = 0, fixed_variant: int = -1,
+                     item_nnz: int = 0, place: int = SPMM_PLACE_DEVICE, threads: int = 0,
+                     validate: bool = True, max_kc: int = 0) -> Handle:
+    L = load_library()
+    rp = _host(row_ptr, np.int64)
+    ci = _host(col_idx, np.int32)
+    va = _host(values, np.float32)
+    n_rows = rp.shape[0] - 1
+    n_cols = n_rows if n_cols is None else int(n_cols)
+    o = spmm_build_opts(tile_rows, tile_cols, fixed_variant, item_nnz, place, threads,
+                        int(bool(validate)), max_kc)
+    out = ctypes.c_void_p()
+    st = L.spmm_build_tiles(n_rows, n_cols, rp.ctypes.data, None if ci is None or ci.size == 0 else ci.ctypes.data,
+                            None if va is None else va.ctypes.data, ctypes.byref(o), ctypes.byref(out))
+    _check(st, "spmm_build_tiles")
+    return Handle(out.value, n_rows, n_cols)
+
+
+def spmm_destroy(h: Handle):
+    load_library().spmm_destroy(ctypes.c_void_p(h.ptr))
+
+
+def _xdtype(X, dtype):
+    if dtype is not None:
+        return dtype
+    name = str(getattr(X, "dtype", "float32"))
+    if "bfloat16" in name:
+        return SPMM_X_BF16
+    if "uint8" in name or "float8" in name:
+        return SPMM_X_FP8_E4M3
+    return SPMM_X_F32
+
+
+def spmm_run(h: Handle, X, Y, k: int | None = None, ldx: int | None = None, dtype: int | None = None,
+             col_scale=None, ldy: int | None = None, stream=None):
+    """Y = A X on the device.  X, Y: 2-D row-major device tensors (or pointers
+    with k/ldx/ldy given); X's dtype selects F32/BF16/FP8 unless ``dtype``."""
+    L = load_library()
+    if k is None:
+        k = X.shape[1]
+    if ldx is None:
+        ldx = X.stride(0)
+    if ldy is None:
+        ldy = Y.stride(0)
+    st = L.spmm_run(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
+                    int(ldy), _stream(stream, X))
+    _check(st, "spmm_run")
+
+
+def spmm_get_stats(h: Handle) -> dict:
+    s = spmm_stats_t()
+    _check(load_library().spmm_get_stats(h.ptr, ctypes.byref(s)), "spmm_get_stats")
+    d = {name: getattr(s, name) for name, _ in spmm_stats_t._fields_[:-2]}
+    d["variant_tiles"] = list(s.variant_tiles)
+    d["variant_nnz"] = list(s.variant_nnz)
+    return d
+
+
+def spmm_decode_tiles(h: Handle, nnz: int, weighted: bool = False):
+    """CSR (row_ptr, col[, val]) rebuilt from the encoded work items."""
+    rp = np.empty(h.n_rows + 1, dtype=np.int64)
+    ci = np.empty(max(nnz, 1), dtype=np.int32)
+    va = np.empty(max(nnz, 1), dtype=np.float32) if weighted else None
+    st = load_library().spmm_decode_tiles(h.ptr, rp.ctypes.data, ci.ctypes.data,
+                                          None if va is None else va.ctypes.data)
+    _check(st, "spmm_decode_tiles")
+    return (rp, ci[:nnz], va[:nnz]) if weighted else (rp, ci[:nnz])
+
+
+def spmm_model_tiles(row_ptr, col_idx, t: int, n_cols: int | None = None):
+    """(non-empty tiles, sum nnr, sum nnc) of the paper's t x t tiling."""
+    rp = _host(row_ptr, np.int64)
+    ci = _host(col_idx, np.int32)
+    n_rows = rp.shape[0] - 1
+    n_cols = n_rows if n_cols is None else int(n_cols)
+    T, R, C = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    st = load_library().spmm_model_tiles(n_rows, n_cols, rp.ctypes.data,
+                                         None if ci.size == 0 else ci.ctypes.data, int(t),
+                                         ctypes.byref(T), ctypes.byref(R), ctypes.byref(C))
+    _check(st, "spmm_model_tiles")
+    return T.value, R.value, C.value

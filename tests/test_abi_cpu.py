@@ -1,0 +1,144 @@
+"""CPU checks of the C ABI: every declared symbol is exported, argument
+errors are reported, and the host-side tile encoding round-trips exactly
+(decoded with the kernels' indexing).  No GPU is touched here."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1602_02864_amd as pk
+import synth
+
+
+def test_library_exports_every_header_symbol():
+    L = pk.load_library()
+    names = pk.header_functions()
+    assert "spmm_run" in names and "spmm_build_tiles" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _err(fn, *a, **kw):
+    with pytest.raises(pk.SpmmError) as ei:
+        fn(*a, **kw)
+    return ei.value
+
+
+def test_build_rejects_bad_options_and_csr():
+    rp, col = synth.small_random_csr(20, 0.2, 1)
+    assert _err(pk.spmm_build_tiles, rp, col, tile_rows=5000).status == pk.SPMM_EINVAL
+    assert _err(pk.spmm_build_tiles, rp, col, tile_cols=1000).status == pk.SPMM_EINVAL
+    assert _err(pk.spmm_build_tiles, rp, col, fixed_variant=9).status == pk.SPMM_EINVAL
+    bad = col.copy()
+    bad[0] = 25
+    e = _err(pk.spmm_build_tiles, rp, bad)
+    assert e.status == pk.SPMM_EINVAL and "range" in pk.spmm_last_error()
+    uns = col.copy()
+    r = int(np.argmax(np.diff(rp) >= 2))
+    uns[rp[r]], uns[rp[r] + 1] = uns[rp[r] + 1], uns[rp[r]]
+    assert _err(pk.spmm_build_tiles, rp, uns).status == pk.SPMM_EINVAL
+    pk.spmm_build_tiles(rp, uns, validate=False).close()   # unsorted allowed without validation
+    rp2 = rp.copy()
+    rp2[3] = rp2[4] + 1
+    assert _err(pk.spmm_build_tiles, rp2, col).status == pk.SPMM_EINVAL
+
+
+def test_null_handle_and_args():
+    L = pk.load_library()
+    assert L.spmm_run(None, None, 4, 4, 0, None, None, 4, None) == pk.SPMM_EINVAL
+    assert L.spmm_get_stats(None, None) == pk.SPMM_EINVAL
+    L.spmm_destroy(None)
+
+
+def test_run_argument_checks_before_device():
+    rp, col = synth.small_random_csr(20, 0.2, 1)
+    h = pk.spmm_build_tiles(rp, col)
+    L = pk.load_library()
+    fake = 1 << 20
+    for k, ldx, ldy, dt, sc in [(0, 4, 4, 0, None), (65, 65, 65, 0, None), (4, 3, 4, 0, None),
+                                (4, 4, 2, 0, None), (4, 4, 4, 7, None), (4, 4, 4, 2, None),
+                                (4, 4, 4, 0, fake)]:
+        assert L.spmm_run(h.ptr, fake, k, ldx, dt, sc, fake, ldy, None) == pk.SPMM_EINVAL
+    assert L.spmm_run(h.ptr, None, 4, 4, 0, None, fake, 4, None) == pk.SPMM_EINVAL
+    h.close()
+
+
+GEOMS = [dict(), dict(tile_rows=16, tile_cols=32), dict(tile_rows=1, tile_cols=1),
+         dict(tile_rows=100, tile_cols=256, item_nnz=64), dict(tile_rows=4096, tile_cols=65536, item_nnz=1)]
+
+
+@pytest.mark.parametrize("geom", GEOMS)
+@pytest.mark.parametrize("variant", range(pk.SPMM_NUM_VARIANTS))
+def test_encode_decode_roundtrip(geom, variant):
+    rp, col = synth.rmat_csr(11, 8, seed=3)
+    h = pk.spmm_build_tiles(rp, col, fixed_variant=variant, **geom)
+    drp, dcol = pk.spmm_decode_tiles(h, col.shape[0])
+    assert np.array_equal(drp, rp) and np.array_equal(dcol, col)
+    st = pk.spmm_get_stats(h)
+    assert st["nnz"] == col.shape[0]
+    assert sum(st["variant_nnz"]) == col.shape[0]
+    assert st["variant_nnz"][variant] == col.shape[0]
+    h.close()
+
+
+def test_encode_decode_weighted_rectangular_ragged():
+    n_rows, n_cols = 1000, 3001
+    d = synth.draws(synth.stream_key(9, 12), 0, n_rows * 6)
+    rows = np.repeat(np.arange(n_rows), 6)
+    cols = (d % np.uint64(n_cols)).astype(np.int64)
+    pairs = np.unique(rows * n_cols + cols)
+    r, c = pairs // n_cols, pairs % n_cols
+    rp = np.zeros(n_rows + 1, np.int64)
+    np.add.at(rp, r + 1, 1)
+    rp = np.cumsum(rp)
+    col = c.astype(np.int32)
+    val = synth.uniform(col.shape[0], 1, seed=3)[:, 0]
+    for v in range(pk.SPMM_NUM_VARIANTS):
+        h = pk.spmm_build_tiles(rp, col, val, n_cols=n_cols, tile_rows=37, tile_cols=512,
+                                fixed_variant=v, item_nnz=300)
+        drp, dcol, dval = pk.spmm_decode_tiles(h, col.shape[0], weighted=True)
+        assert np.array_equal(drp, rp) and np.array_equal(dcol, col) and np.array_equal(dval, val)
+        h.close()
+
+
+def test_empty_matrix_and_empty_rows():
+    rp = np.zeros(11, np.int64)
+    h = pk.spmm_build_tiles(rp, np.zeros(0, np.int32))
+    st = pk.spmm_get_stats(h)
+    assert st["nnz"] == 0 and st["n_tiles"] == 0
+    drp, dcol = pk.spmm_decode_tiles(h, 0)
+    assert np.array_equal(drp, rp)
+    h.close()
+    h = pk.spmm_build_tiles(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    h.close()
+
+
+def test_tile_stats_match_definition():
+    rp, col = synth.rmat_csr(12, 8, seed=2)
+    n = 1 << 12
+    h, w = 64, 128
+    hd = pk.spmm_build_tiles(rp, col, tile_rows=h, tile_cols=w)
+    st = pk.spmm_get_stats(hd)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    tiles = (rows // h) * (n // w) + col // w
+    assert st["n_tiles"] == np.unique(tiles).size
+    assert st["sum_nnr"] == np.unique(tiles * n + rows).size
+    assert st["sum_nnc"] == np.unique(tiles * n + col).size
+    hd.close()
+
+
+@pytest.mark.parametrize("t", [1, 7, 64, 16384])
+def test_model_tiles_and_paper_formula(t):
+    rp, col = synth.rmat_csr(12, 8, seed=4, symmetrize=True)
+    n = 1 << 12
+    T, R, C = pk.spmm_model_tiles(rp, col, t)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    nstrip = (n + t - 1) // t
+    tile = (rows // t) * nstrip + col // t
+    assert T == np.unique(tile).size
+    assert R == np.unique(tile * n + rows).size
+    assert C == np.unique(tile * n + col).size
+    # S_SCSR / S_DCSC within the paper's bound when nnr ~ nnc (symmetric A)
+    r = oracle.scsr_bytes(R, col.shape[0], 0) / oracle.dcsc_bytes(C, col.shape[0], 0)
+    assert 0.4 <= r < 1.0 or R != C
