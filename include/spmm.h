@@ -143,6 +143,27 @@ spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_
                        const float* col_scale, float* Y, int64_t ldy, hipStream_t s);
 
 /*
+ * Quantise X for the reduced-precision SpMM paths (not in the paper; halves
+ * or quarters the X bytes every SpMM gathers).
+ *   X     : device FP32, n x k, row stride ldx >= k.
+ *   dt    : SPMM_X_BF16 -> Xq is uint16 BF16 codes, round to nearest even.
+ *           SPMM_X_FP8_E4M3 -> Xq is uint8 OCP E4M3 codes of fp32(X[i][j] * s_j),
+ *           nearest with ties to even, saturating at +-448.
+ *   Xq    : device, n x k codes, row stride ldq >= k (elements).
+ *   col_scale : device float[k]; FP8 only (NULL for BF16).  Unless flags has
+ *           SPMM_QUANT_SCALES_GIVEN, it is overwritten with
+ *           s_j = 448 / max_i |X[i][j]| (FP32 division; 1 for a zero column);
+ *           with the flag it is read as given.  Pass the same array to
+ *           spmm_run, which divides Y's column j by s_j.
+ *   flags : 0 or SPMM_QUANT_SCALES_GIVEN.
+ * Asynchronous on s.  Errors: SPMM_EINVAL, SPMM_EHIP.
+ */
+#define SPMM_QUANT_SCALES_GIVEN 1u
+spmm_status_t spmm_quantize_x(const float* X, int64_t n, int k, int64_t ldx, spmm_xdtype_t dt,
+                              void* Xq, int64_t ldq, float* col_scale, uint32_t flags,
+                              hipStream_t s);
+
+/*
  * Rebuild the CSR of A from the encoded work items (host copy of the tile
  * payload), walking them with the same indexing as the kernels.  A check of
  * the encoding: the result equals the CSR given to spmm_build_tiles.

@@ -65,6 +65,14 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch
+    # first makes libspmm.so bind to that one runtime, so device pointers and
+    # streams from torch tensors are valid in the library; loading the
+    # library first would map a second, separate runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     i64, i32, vp, u64p = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)
     L.spmm_last_error.restype = ctypes.c_char_p
@@ -76,6 +84,8 @@ def load_library():
     L.spmm_destroy.argtypes = [vp]
     L.spmm_run.restype = i32
     L.spmm_run.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp]
+    L.spmm_quantize_x.restype = i32
+    L.spmm_quantize_x.argtypes = [vp, i64, i32, i64, i32, vp, i64, vp, ctypes.c_uint32, vp]
     L.spmm_get_stats.restype = i32
     L.spmm_get_stats.argtypes = [vp, ctypes.POINTER(spmm_stats_t)]
     L.spmm_decode_tiles.restype = i32
@@ -200,6 +210,23 @@ def spmm_run(h: Handle, X, Y, k: int | None = None, ldx: int | None = None, dtyp
     st = L.spmm_run(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
                     int(ldy), _stream(stream, X))
     _check(st, "spmm_run")
+
+
+SPMM_QUANT_SCALES_GIVEN = 1
+
+
+def spmm_quantize_x(X, Xq, dtype: int, col_scale=None, flags: int = 0, n: int | None = None,
+                    k: int | None = None, ldx: int | None = None, ldq: int | None = None,
+                    stream=None):
+    """Quantise FP32 X (device) into BF16 / FP8-E4M3 codes in Xq (device)."""
+    L = load_library()
+    n = X.shape[0] if n is None else n
+    k = X.shape[1] if k is None else k
+    ldx = X.stride(0) if ldx is None else ldx
+    ldq = Xq.stride(0) if ldq is None else ldq
+    st = L.spmm_quantize_x(_ptr(X), int(n), int(k), int(ldx), int(dtype), _ptr(Xq), int(ldq),
+                           _ptr(col_scale), int(flags), _stream(stream, X))
+    _check(st, "spmm_quantize_x")
 
 
 def spmm_get_stats(h: Handle) -> dict:

@@ -90,7 +90,7 @@ spmm_status_t ensure_uploaded(spmm::Handle& H) {
 }
 
 spmm_status_t ensure_partials(spmm::Handle& H) {
-    const uint64_t need = H.enc.n_parts * (uint64_t)H.h * spmm::kMaxKc;
+    const uint64_t need = H.enc.n_parts * (uint64_t)H.h * (uint64_t)spmm::kc_cap(H);
     if (need == 0 || need <= H.part_cap) return SPMM_OK;
     if (H.d_part) hipFree(H.d_part);
     H.d_part = nullptr;
@@ -205,6 +205,22 @@ spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_
     } catch (const std::exception& e) {
         return fail(SPMM_EINVAL, e.what());
     }
+}
+
+spmm_status_t spmm_quantize_x(const float* X, int64_t n, int k, int64_t ldx, spmm_xdtype_t dt,
+                              void* Xq, int64_t ldq, float* col_scale, uint32_t flags,
+                              hipStream_t s) {
+    if (n < 0 || k < 1 || k > 64) return fail(SPMM_EINVAL, "need n >= 0 and 1 <= k <= 64");
+    if (ldx < k || ldq < k) return fail(SPMM_EINVAL, "ldx and ldq must be >= k");
+    if (dt != SPMM_X_BF16 && dt != SPMM_X_FP8_E4M3)
+        return fail(SPMM_EINVAL, "dt must be SPMM_X_BF16 or SPMM_X_FP8_E4M3");
+    if ((dt == SPMM_X_FP8_E4M3) != (col_scale != nullptr))
+        return fail(SPMM_EINVAL, "col_scale must be given exactly when dt is FP8");
+    if (flags & ~SPMM_QUANT_SCALES_GIVEN) return fail(SPMM_EINVAL, "unknown flags");
+    if (n > 0 && (!X || !Xq)) return fail(SPMM_EINVAL, "X or Xq is NULL");
+    hipError_t e = spmm::launch_quantize(X, n, k, ldx, dt, Xq, ldq, col_scale,
+                                         (flags & SPMM_QUANT_SCALES_GIVEN) != 0, s);
+    return e == hipSuccess ? SPMM_OK : hip_fail(e, "quantize launch");
 }
 
 spmm_status_t spmm_get_stats(spmm_handle_t h, spmm_stats_t* out) {

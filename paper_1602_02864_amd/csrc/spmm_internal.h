@@ -1,6 +1,7 @@
 // Internal types shared by the host builder, the ABI layer and the kernels.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <functional>
 #include <string>
@@ -101,6 +102,14 @@ struct Handle {
     bool uploaded = false;
 };
 
+// Widest column chunk whose per-wavefront accumulator (h x kc FP32) fits
+// in 64 KB of LDS, bounded by the handle's max_kc.
+inline int kc_cap(const Handle& H) {
+    int cap = H.max_kc;
+    while (cap > 1 && (uint64_t)H.h * cap * 4u > 65536u) cap >>= 1;
+    return cap;
+}
+
 // builder.cpp
 spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* col,
                               const float* val, bool validate, std::string& err);
@@ -132,5 +141,9 @@ struct RunArgs {
     uint32_t* count;             // device, n_combine counters, zero between launches
 };
 hipError_t launch_spmm(const Handle& H, const RunArgs& a);
+
+// quant_kernels.hip
+hipError_t launch_quantize(const float* X, int64_t n, int k, int64_t ldx, int dtype, void* Xq,
+                           int64_t ldq, float* col_scale, bool scales_given, hipStream_t s);
 
 }  // namespace spmm

@@ -299,9 +299,7 @@ hipError_t launch_vw(const Handle& H, const RunArgs& a, const XT* X, float* Y,
 template <typename XT>
 hipError_t launch_typed(const Handle& H, const RunArgs& a) {
     const XT* X = static_cast<const XT*>(a.X);
-    // widest chunk whose accumulator (h x kc floats per wavefront) fits 64 KB
-    int cap = H.max_kc;
-    while (cap > 1 && (uint64_t)H.h * cap * 4u > 65536u) cap >>= 1;
+    const int cap = kc_cap(H);
     for (int c0 = 0; c0 < a.k;) {
         const int rem = a.k < c0 + cap ? a.k - c0 : cap;
         const int kc = rem >= 32 ? 32 : rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;

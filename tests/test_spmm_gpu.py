@@ -48,7 +48,8 @@ def test_fp32_within_1e6(graph, variant):
 
 GEOMS = [dict(tile_rows=16, tile_cols=256, item_nnz=100),      # many splits, tiny tiles
          dict(tile_rows=1, tile_cols=1 << 16),                 # one row per tile row
-         dict(tile_rows=4096, tile_cols=1024, item_nnz=1),     # one unit per item
+         dict(tile_rows=64, tile_cols=64, item_nnz=1),         # one unit per item
+         dict(tile_rows=4096, tile_cols=1024, item_nnz=64),    # tall tile rows, tiny items
          dict(tile_rows=300, tile_cols=8192, item_nnz=5000),   # ragged tile rows
          dict(max_kc=32)]
 
