@@ -128,7 +128,7 @@ def main() -> int:
     ms_step = wall * 1e3 / args.steps
     value = flop_step / (ms_step * 1e-3) / 1e9
 
-    max_kc = args.max_kc or 16
+    max_kc = args.max_kc or 32
     per_k = {}
     for k in ks:
         mb = model_bytes(T, R, C, nnz, n, k)

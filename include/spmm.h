@@ -83,17 +83,22 @@ typedef enum {
 
 /* Build options.  A zero-initialised struct selects every default. */
 typedef struct {
-    uint32_t tile_rows;      /* h: rows per tile row; 0 -> 256; 1..4096          */
+    uint32_t tile_rows;      /* h: rows per tile row; 0 -> 64; 1..4096           */
     uint32_t tile_cols;      /* w: columns per tile; 0 -> 65536; power of 2,
                                  <= 65536 (16-bit local column index)           */
     int32_t fixed_variant;   /* variant of every tile; < 0 -> SPMM_VAR_HYBRID    */
     uint32_t item_nnz;       /* target non-zeros per work item (one wavefront);
-                                 tile rows above it are split; 0 -> 16384         */
+                                 longer rows are split; 0 -> 16384, <= 131072      */
     uint32_t place;          /* spmm_place_t                                     */
     uint32_t threads;        /* host threads for the build; 0 -> all cores       */
     uint32_t validate;       /* 1 -> reject unsorted/duplicate/out-of-range CSR  */
     uint32_t max_kc;         /* widest block of X columns one kernel launch
-                                 accumulates: 16 or 32; 0 -> 16                   */
+                                 accumulates: 16 or 32; 0 -> 32                   */
+    uint32_t keep_order;     /* 0 (default): tiles index columns by descending
+                                 in-degree, and spmm_run first gathers X into that
+                                 row order (a handle-owned buffer), so the X rows
+                                 of hub columns are contiguous and cache-resident;
+                                 1: tiles keep the given column order             */
 } spmm_build_opts;
 
 typedef struct spmm_handle_s* spmm_handle_t;

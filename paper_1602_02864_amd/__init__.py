@@ -44,7 +44,8 @@ class spmm_build_opts(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_uint32), ("tile_cols", ctypes.c_uint32),
                 ("fixed_variant", ctypes.c_int32), ("item_nnz", ctypes.c_uint32),
                 ("place", ctypes.c_uint32), ("threads", ctypes.c_uint32),
-                ("validate", ctypes.c_uint32), ("max_kc", ctypes.c_uint32)]
+                ("validate", ctypes.c_uint32), ("max_kc", ctypes.c_uint32),
+                ("keep_order", ctypes.c_uint32)]
 
 
 class spmm_stats_t(ctypes.Structure):
@@ -165,7 +166,7 @@ class Handle:
 def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *,
                      tile_rows: int = 0, tile_cols: int = 0, fixed_variant: int = -1,
                      item_nnz: int = 0, place: int = SPMM_PLACE_DEVICE, threads: int = 0,
-                     validate: bool = True, max_kc: int = 0) -> Handle:
+                     validate: bool = True, max_kc: int = 0, keep_order: bool = False) -> Handle:
     L = load_library()
     rp = _host(row_ptr, np.int64)
     ci = _host(col_idx, np.int32)
@@ -173,7 +174,7 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
     n_rows = rp.shape[0] - 1
     n_cols = n_rows if n_cols is None else int(n_cols)
     o = spmm_build_opts(tile_rows, tile_cols, fixed_variant, item_nnz, place, threads,
-                        int(bool(validate)), max_kc)
+                        int(bool(validate)), max_kc, int(bool(keep_order)))
     out = ctypes.c_void_p()
     st = L.spmm_build_tiles(n_rows, n_cols, rp.ctypes.data, None if ci is None or ci.size == 0 else ci.ctypes.data,
                             None if va is None else va.ctypes.data, ctypes.byref(o), ctypes.byref(out))

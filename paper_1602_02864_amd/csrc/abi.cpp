@@ -34,6 +34,11 @@ void free_device(spmm::Handle& H) {
     if (H.d_combine) hipFree(H.d_combine);
     if (H.d_part) hipFree(H.d_part);
     if (H.d_count) hipFree(H.d_count);
+    if (H.d_col_old) hipFree(H.d_col_old);
+    if (H.d_xperm) hipFree(H.d_xperm);
+    H.d_col_old = nullptr;
+    H.d_xperm = nullptr;
+    H.xperm_bytes = 0;
     if (H.h_blob) hipHostFree(H.h_blob);
     H.d_blob = H.h_blob = nullptr;
     H.d_items = nullptr;
@@ -76,6 +81,13 @@ spmm_status_t upload(spmm::Handle& H) {
         return fail(SPMM_ENOMEM, "hipMalloc(combine counters) failed");
     if ((e = hipMemset(H.d_count, 0, nc * sizeof(uint32_t))) != hipSuccess)
         return hip_fail(e, "hipMemset(combine counters)");
+    if (H.relabel && H.n_cols > 0) {
+        if ((e = hipMalloc(&H.d_col_old, sizeof(int32_t) * (size_t)H.n_cols)) != hipSuccess)
+            return fail(SPMM_ENOMEM, "hipMalloc(column order) failed");
+        if ((e = hipMemcpy(H.d_col_old, H.col_old.data(), sizeof(int32_t) * (size_t)H.n_cols,
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy(column order)");
+    }
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     if (H.place == SPMM_PLACE_PINNED_HOST) std::vector<uint8_t>().swap(E.blob);  // pinned copy replaces it
     H.uploaded = true;
@@ -90,7 +102,7 @@ spmm_status_t ensure_uploaded(spmm::Handle& H) {
 }
 
 spmm_status_t ensure_partials(spmm::Handle& H) {
-    const uint64_t need = H.enc.n_parts * (uint64_t)H.h * (uint64_t)spmm::kc_cap(H);
+    const uint64_t need = H.enc.n_parts * (uint64_t)spmm::kc_cap(H);
     if (need == 0 || need <= H.part_cap) return SPMM_OK;
     if (H.d_part) hipFree(H.d_part);
     H.d_part = nullptr;
@@ -130,12 +142,13 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         if (row_ptr[n_rows] > 0 && !col_idx) return fail(SPMM_EINVAL, "col_idx is NULL");
         spmm_build_opts o{};
         if (opts) o = *opts;
-        if (o.max_kc == 0) o.max_kc = 16;
+        if (o.max_kc == 0) o.max_kc = 32;
         if (o.max_kc != 16 && o.max_kc != 32) return fail(SPMM_EINVAL, "max_kc must be 16 or 32");
         if (o.tile_rows == 0) o.tile_rows = spmm::kDefaultTileRows;
         if (o.tile_cols == 0) o.tile_cols = spmm::kDefaultTileCols;
         if (o.item_nnz == 0) o.item_nnz = spmm::kDefaultItemNnz;
         if (o.tile_rows > spmm::kMaxTileRows) return fail(SPMM_EINVAL, "tile_rows must be <= 4096");
+        if (o.item_nnz > spmm::kMaxItemNnz) return fail(SPMM_EINVAL, "item_nnz must be <= 131072");
         if (!is_pow2(o.tile_cols) || o.tile_cols > 65536)
             return fail(SPMM_EINVAL, "tile_cols must be a power of two <= 65536");
         if (o.fixed_variant >= SPMM_NUM_VARIANTS) return fail(SPMM_EINVAL, "unknown variant");
@@ -151,6 +164,7 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         H.threads = o.threads;
         H.place = o.place;
         H.max_kc = (int)o.max_kc;
+        H.relabel = o.keep_order == 0;
         std::string err;
         spmm_status_t st = spmm::build_canonical(H, row_ptr, col_idx, values, o.validate != 0, err);
         if (st != SPMM_OK) return fail(st, err);
@@ -187,6 +201,24 @@ spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_
         a.X = X;
         a.k = k;
         a.ldx = ldx;
+        if (H.relabel && H.n_cols > 0) {
+            // gather X into the relabelled row order, rows padded to 4 elements
+            const int esize = dt == SPMM_X_F32 ? 4 : dt == SPMM_X_BF16 ? 2 : 1;
+            const int64_t ldp = (k + 3) / 4 * 4;
+            const uint64_t need = (uint64_t)H.n_cols * ldp * esize;
+            if (need > H.xperm_bytes) {
+                if (H.d_xperm) hipFree(H.d_xperm);
+                H.d_xperm = nullptr;
+                H.xperm_bytes = 0;
+                if (hipMalloc(&H.d_xperm, need) != hipSuccess)
+                    return fail(SPMM_ENOMEM, "hipMalloc(relabelled X) failed");
+                H.xperm_bytes = need;
+            }
+            hipError_t pe = spmm::launch_permute_rows(X, ldx, k, esize, H.d_col_old, H.n_cols, H.d_xperm, ldp, s);
+            if (pe != hipSuccess) return hip_fail(pe, "X permutation launch");
+            a.X = H.d_xperm;
+            a.ldx = ldp;
+        }
         a.dtype = dt;
         a.col_scale = col_scale;
         a.Y = Y;

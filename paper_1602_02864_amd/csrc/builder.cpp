@@ -85,6 +85,32 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
         return SPMM_EINVAL;
     }
 
+    // Column relabelling by descending in-degree (ties by column id): a
+    // counting sort over degrees, stable in the original order.
+    const int32_t* cmap = nullptr;
+    if (H.relabel) {
+        const int64_t m = H.n_cols;
+        std::vector<uint32_t> indeg((size_t)m, 0);
+        parallel_for((uint64_t)n, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
+            for (int64_t p = row_ptr[a]; p < row_ptr[b]; ++p)
+                __atomic_fetch_add(&indeg[col[p]], 1u, __ATOMIC_RELAXED);
+        });
+        uint32_t maxd = 0;
+        for (int64_t c = 0; c < m; ++c) maxd = std::max(maxd, indeg[c]);
+        std::vector<uint64_t> start((size_t)maxd + 2, 0);
+        for (int64_t c = 0; c < m; ++c) start[maxd - indeg[c] + 1]++;
+        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+        H.col_new.resize((size_t)m);
+        H.col_old.resize((size_t)m);
+        for (int64_t c = 0; c < m; ++c) {
+            const uint64_t r = start[maxd - indeg[c]]++;
+            H.col_new[c] = (int32_t)r;
+            H.col_old[r] = (int32_t)c;
+        }
+        cmap = H.col_new.data();
+    }
+    auto colmap = [cmap](int32_t c) -> uint32_t { return cmap ? (uint32_t)cmap[c] : (uint32_t)c; };
+
     // Pass 1: non-empty tiles per slab.
     std::vector<uint64_t> ntile(H.n_slabs + 1, 0);
     const uint32_t nstrip = (uint32_t)H.n_strips;
@@ -95,7 +121,7 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
             int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(n, r0 + H.h);
             used.clear();
             for (int64_t p = row_ptr[r0]; p < row_ptr[r1]; ++p) {
-                uint32_t J = (uint32_t)col[p] >> H.wshift;
+                uint32_t J = colmap(col[p]) >> H.wshift;
                 if (cnt[J]++ == 0) used.push_back(J);
             }
             ntile[s + 1] = used.size();
@@ -127,7 +153,7 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
             int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(n, r0 + H.h);
             used.clear();
             for (int64_t p = row_ptr[r0]; p < row_ptr[r1]; ++p) {
-                uint32_t J = (uint32_t)col[p] >> H.wshift;
+                uint32_t J = colmap(col[p]) >> H.wshift;
                 if (cnt[J]++ == 0) used.push_back(J);
             }
             std::sort(used.begin(), used.end());
@@ -146,10 +172,30 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
             for (int64_t r = r0; r < r1; ++r) {
                 uint32_t rl = (uint32_t)(r - r0);
                 for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
-                    uint32_t c = (uint32_t)col[p];
+                    uint32_t c = colmap(col[p]);
                     uint64_t q = pos[c >> H.wshift]++;
                     H.ent[q] = (rl << 16) | (c & (H.w - 1));
                     if (val) H.val[q] = val[p];
+                }
+            }
+            if (cmap) {
+                // relabelled columns arrive unordered within a row: sort each
+                // tile's entries by (row, column), carrying the values along
+                for (uint64_t ti = H.slab_tiles[s]; ti < H.slab_tiles[s + 1]; ++ti) {
+                    const Tile& tl = H.tiles[ti];
+                    uint32_t* E = H.ent.data() + tl.ent_begin;
+                    if (!val) {
+                        std::sort(E, E + tl.nnz);
+                    } else {
+                        std::vector<std::pair<uint32_t, float>> tmp(tl.nnz);
+                        for (uint32_t i = 0; i < tl.nnz; ++i) tmp[i] = {E[i], H.val[tl.ent_begin + i]};
+                        std::sort(tmp.begin(), tmp.end(),
+                                  [](const auto& x, const auto& y) { return x.first < y.first; });
+                        for (uint32_t i = 0; i < tl.nnz; ++i) {
+                            E[i] = tmp[i].first;
+                            H.val[tl.ent_begin + i] = tmp[i].second;
+                        }
+                    }
                 }
             }
             for (uint64_t ti = H.slab_tiles[s]; ti < H.slab_tiles[s + 1]; ++ti) {
@@ -188,180 +234,214 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
 
 namespace {
 
+// A run of one row inside one tile: entries ent[ent, ent + len).
 struct Seg {
     uint32_t J, row, len;
-    uint64_t ent;  // first canonical entry
+    uint64_t ent;
 };
-
-inline uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
 
 struct ChunkOut {
     std::vector<ItemDesc> items;  // blob_off relative to the chunk blob
     std::vector<uint32_t> nnz;
     std::vector<uint8_t> blob;
+    std::vector<CombineDesc> combine;  // part_* relative to the chunk's first part
+    uint32_t n_parts = 0;
     uint64_t vt[SPMM_NUM_VARIANTS] = {}, vn[SPMM_NUM_VARIANTS] = {};
 };
 
-// Encode one slab into items appended to `out`.
-void encode_slab(const Handle& H, uint64_t s, ChunkOut& out, std::vector<uint32_t>& coo_ent,
-                 std::vector<float>& coo_val, std::vector<uint32_t>& coo_J,
-                 std::vector<Seg>& lr, std::vector<Seg>& wr) {
-    coo_ent.clear();
-    coo_val.clear();
-    coo_J.clear();
-    lr.clear();
-    wr.clear();
+struct Scratch {
+    std::vector<uint32_t> rdeg;
+    std::vector<uint64_t> cursor;
+    std::vector<Seg> segs, lr, wr, piece;
+    std::vector<uint32_t> coo_ent, coo_J, Js;
+    std::vector<float> coo_val;
+};
+
+// Encode the row segments `segs` (tile order) as one work item owning local
+// rows [lo, hi) (or, with part >= 0, one piece of the split row lo).
+void emit_item(const Handle& H, uint32_t slab, uint32_t lo, uint32_t hi, int32_t part,
+               uint32_t cid, const std::vector<Seg>& segs, ChunkOut& out, Scratch& S) {
     const bool hv = H.has_val;
-    const uint32_t C = H.item_nnz;
-    for (uint64_t t = H.slab_tiles[s]; t < H.slab_tiles[s + 1]; ++t) {
-        const Tile& tl = H.tiles[t];
-        const int v = H.variant[t];
-        out.vt[v] += 1;
-        out.vn[v] += tl.nnz;
-        const uint32_t* E = H.ent.data() + tl.ent_begin;
-        uint32_t i = 0;
-        while (i < tl.nnz) {
-            uint32_t r = E[i] >> 16, j = i;
-            while (j < tl.nnz && (E[j] >> 16) == r) ++j;
-            uint32_t len = j - i;
-            if (v == SPMM_VAR_COO || len == 1) {
-                for (uint32_t q = i; q < j; ++q) {
-                    coo_ent.push_back(E[q]);
-                    if (hv) coo_val.push_back(H.val[tl.ent_begin + q]);
-                    coo_J.push_back(tl.J);
-                }
-            } else if (v == SPMM_VAR_ROW || (v == SPMM_VAR_HYBRID && len < kWaveRowMin)) {
-                for (uint32_t q = i; q < j; q += kRowLaneMax)
-                    lr.push_back({tl.J, r, std::min(kRowLaneMax, j - q), tl.ent_begin + q});
-            } else {
-                for (uint32_t q = i; q < j; q += C)
-                    wr.push_back({tl.J, r, std::min(C, j - q), tl.ent_begin + q});
-            }
-            i = j;
-        }
-    }
-    std::stable_sort(lr.begin(), lr.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
-
-    // Cut the unit sequence (COO entries, then row segments, then wavefront
-    // segments) into items of about C non-zeros.
-    struct Range { uint32_t ca, cb, la, lb, wa, wb, nnz; };
-    std::vector<Range> ranges;
-    Range cur{0, 0, 0, 0, 0, 0, 0};
-    auto close = [&]() {
-        ranges.push_back(cur);
-        cur = {cur.cb, cur.cb, cur.lb, cur.lb, cur.wb, cur.wb, 0};
-    };
-    const uint32_t nc = (uint32_t)coo_ent.size(), nl = (uint32_t)lr.size(), nw = (uint32_t)wr.size();
-    while (cur.cb < nc) {
-        uint32_t take = std::min(nc - cur.cb, C - cur.nnz);
-        cur.cb += take;
-        cur.nnz += take;
-        if (cur.nnz >= C) close();
-    }
-    while (cur.lb < nl) {
-        cur.nnz += lr[cur.lb++].len;
-        if (cur.nnz >= C) close();
-    }
-    while (cur.wb < nw) {
-        cur.nnz += wr[cur.wb++].len;
-        if (cur.nnz >= C) close();
-    }
-    if (cur.nnz > 0 || ranges.empty()) ranges.push_back(cur);
-
-    std::vector<uint32_t> Js;
-    for (const Range& R : ranges) {
-        ItemDesc d{};
-        d.slab = (uint32_t)s;
-        d.part = ranges.size() > 1 ? 0 : -1;  // fixed up globally
-        d.n_coo = R.cb - R.ca;
-        // strip runs of the COO entries
-        uint32_t n_ct = 0;
-        for (uint32_t e = R.ca; e < R.cb; ++e)
-            if (e == R.ca || coo_J[e] != coo_J[e - 1]) ++n_ct;
-        d.n_coo_tiles = n_ct;
-        d.n_lr = R.lb - R.la;
-        d.n_wr = R.wb - R.wa;
-        Js.clear();
-        for (uint32_t q = R.la; q < R.lb; ++q) Js.push_back(lr[q].J);
-        std::sort(Js.begin(), Js.end());
-        Js.erase(std::unique(Js.begin(), Js.end()), Js.end());
-        uint32_t n_cols = 0;
-        for (uint32_t q = R.la; q < R.lb; ++q) n_cols += lr[q].len;
-        for (uint32_t q = R.wa; q < R.wb; ++q) n_cols += wr[q].len;
-
-        uint32_t o = 4 * d.n_coo;
-        if (hv) o += 4 * d.n_coo;  // coo_val at 4 * n_coo
-        o = align_up(o, 8);
-        d.o_coo_tile = o;
-        o += 8 * n_ct;
-        d.o_lr_desc = o;
-        o += 4 * d.n_lr;
-        d.o_lr_start = o;
-        o += 4 * (d.n_lr + 1);
-        d.o_lr_J = o;
-        o += 4 * (uint32_t)Js.size();
-        o = align_up(o, 16);
-        d.o_wr = o;
-        o += 16 * d.n_wr;
-        d.o_cols = o;
-        o += 2 * n_cols;
-        o = align_up(o, 4);
-        d.o_col_val = o;
-        if (hv) o += 4 * n_cols;
-        o = align_up(o, 16);
-
-        const uint64_t base = out.blob.size();
-        d.blob_off = base;
-        out.blob.resize(base + o, 0);
-        uint8_t* P = out.blob.data() + base;
-        uint32_t* pe = reinterpret_cast<uint32_t*>(P);
-        float* pv = reinterpret_cast<float*>(P + 4 * d.n_coo);
-        uint32_t* pt = reinterpret_cast<uint32_t*>(P + d.o_coo_tile);
-        uint32_t ti = 0;
-        for (uint32_t e = R.ca; e < R.cb; ++e) {
-            pe[e - R.ca] = coo_ent[e];
-            if (hv) pv[e - R.ca] = coo_val[e];
-            if (e == R.ca || coo_J[e] != coo_J[e - 1]) {
-                pt[2 * ti] = coo_J[e];
-                pt[2 * ti + 1] = e - R.ca;
-                ++ti;
-            }
-        }
-        uint32_t* pd = reinterpret_cast<uint32_t*>(P + d.o_lr_desc);
-        uint32_t* ps = reinterpret_cast<uint32_t*>(P + d.o_lr_start);
-        uint32_t* pj = reinterpret_cast<uint32_t*>(P + d.o_lr_J);
-        uint32_t* pw = reinterpret_cast<uint32_t*>(P + d.o_wr);
-        uint16_t* pc = reinterpret_cast<uint16_t*>(P + d.o_cols);
-        float* pcv = reinterpret_cast<float*>(P + d.o_col_val);
-        for (size_t q = 0; q < Js.size(); ++q) pj[q] = Js[q];
-        uint32_t cpos = 0;
-        auto put_cols = [&](const Seg& g) {
-            const uint32_t* E = H.ent.data() + g.ent;
+    S.coo_ent.clear();
+    S.coo_val.clear();
+    S.coo_J.clear();
+    S.lr.clear();
+    S.wr.clear();
+    uint32_t nnz = 0;
+    for (const Seg& g : segs) {
+        nnz += g.len;
+        const int v = g.row >> 16;  // the tile's variant rides in the high bits
+        const uint32_t row = g.row & 0xFFFFu;
+        if (v == SPMM_VAR_COO || g.len == 1) {
+            bool first = S.coo_J.empty() || S.coo_J.back() != g.J;
+            if (first) S.coo_J.push_back(g.J);
             for (uint32_t q = 0; q < g.len; ++q) {
-                pc[cpos + q] = (uint16_t)(E[q] & 0xFFFFu);
-                if (hv) pcv[cpos + q] = H.val[g.ent + q];
+                uint32_t e = H.ent[g.ent + q];
+                S.coo_ent.push_back((first && q == 0 ? kCooNewTile : 0u) | e);
+                if (hv) S.coo_val.push_back(H.val[g.ent + q]);
             }
-            cpos += g.len;
-        };
-        for (uint32_t q = R.la; q < R.lb; ++q) {
-            const Seg& g = lr[q];
-            uint32_t ord = (uint32_t)(std::lower_bound(Js.begin(), Js.end(), g.J) - Js.begin());
-            pd[q - R.la] = g.row | (ord << 16);
-            ps[q - R.la] = cpos;
-            put_cols(g);
+        } else if (v == SPMM_VAR_ROW || (v == SPMM_VAR_HYBRID && g.len < kWaveRowMin)) {
+            for (uint32_t q = 0; q < g.len; q += kRowLaneMax)
+                S.lr.push_back({g.J, row, std::min(kRowLaneMax, g.len - q), g.ent + q});
+        } else {
+            S.wr.push_back({g.J, row, g.len, g.ent});
         }
-        ps[d.n_lr] = cpos;
-        for (uint32_t q = R.wa; q < R.wb; ++q) {
-            const Seg& g = wr[q];
-            uint32_t* w4 = pw + 4 * (q - R.wa);
-            w4[0] = g.J;
-            w4[1] = g.row;
-            w4[2] = cpos;
-            w4[3] = g.len;
-            put_cols(g);
+    }
+    std::stable_sort(S.lr.begin(), S.lr.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
+    S.Js.clear();
+    for (const Seg& g : S.lr) S.Js.push_back(g.J);
+    std::sort(S.Js.begin(), S.Js.end());
+    S.Js.erase(std::unique(S.Js.begin(), S.Js.end()), S.Js.end());
+    // interleaved row-lane columns: blocks of 64 segments, stride 64
+    uint32_t lr_cols = 0;
+    for (size_t b = 0; b < S.lr.size(); b += 64) lr_cols += 64u * S.lr[b].len;
+    uint32_t wr_cols = 0;
+    for (const Seg& g : S.wr) wr_cols += g.len;
+
+    ItemDesc d{};
+    d.slab = slab;
+    d.part = part;
+    d.rows = lo | (hi << 16);
+    d.cid = cid;
+    d.n_coo = (uint32_t)S.coo_ent.size();
+    d.n_coo_J = (uint32_t)S.coo_J.size();
+    d.n_lr = (uint32_t)S.lr.size();
+    d.n_lr_J = (uint32_t)S.Js.size();
+    d.n_wr = (uint32_t)S.wr.size();
+    d.n_cols = lr_cols + wr_cols;
+    const ItemLayout L = item_layout(d, hv);
+    const uint64_t base = out.blob.size();
+    d.blob_off = base;
+    out.blob.resize(base + L.bytes, 0);
+    uint8_t* P = out.blob.data() + base;
+    auto* pe = reinterpret_cast<uint32_t*>(P);
+    auto* pv = reinterpret_cast<float*>(P + 4 * (size_t)d.n_coo);
+    auto* pj = reinterpret_cast<uint32_t*>(P + L.o_coo_J);
+    auto* pl = reinterpret_cast<uint32_t*>(P + L.o_lr);
+    auto* plj = reinterpret_cast<uint32_t*>(P + L.o_lr_J);
+    auto* pw = reinterpret_cast<uint32_t*>(P + L.o_wr);
+    auto* pc = reinterpret_cast<uint16_t*>(P + L.o_cols);
+    auto* pcv = reinterpret_cast<float*>(P + L.o_cval);
+    for (uint32_t e = 0; e < d.n_coo; ++e) {
+        pe[e] = S.coo_ent[e];
+        if (hv) pv[e] = S.coo_val[e];
+    }
+    for (uint32_t q = 0; q < d.n_coo_J; ++q) pj[q] = S.coo_J[q];
+    for (uint32_t q = 0; q < d.n_lr_J; ++q) plj[q] = S.Js[q];
+    uint32_t block_base = 0;
+    for (uint32_t q = 0; q < d.n_lr; ++q) {
+        const Seg& g = S.lr[q];
+        if (q % 64 == 0 && q) block_base += 64u * S.lr[q - 64].len;
+        const uint32_t start = block_base + (q % 64);
+        const uint32_t ord = (uint32_t)(std::lower_bound(S.Js.begin(), S.Js.end(), g.J) - S.Js.begin());
+        pl[2 * q] = g.row | (ord << 12);
+        pl[2 * q + 1] = start | (g.len << kLrStartBits);
+        for (uint32_t t = 0; t < g.len; ++t) {
+            pc[start + 64u * t] = (uint16_t)(H.ent[g.ent + t] & 0xFFFFu);
+            if (hv) pcv[start + 64u * t] = H.val[g.ent + t];
         }
-        out.items.push_back(d);
-        out.nnz.push_back(R.nnz);
+    }
+    uint32_t cpos = lr_cols;
+    for (uint32_t q = 0; q < d.n_wr; ++q) {
+        const Seg& g = S.wr[q];
+        pw[4 * q] = g.J;
+        pw[4 * q + 1] = g.row;
+        pw[4 * q + 2] = cpos;
+        pw[4 * q + 3] = g.len;
+        for (uint32_t t = 0; t < g.len; ++t) {
+            pc[cpos + t] = (uint16_t)(H.ent[g.ent + t] & 0xFFFFu);
+            if (hv) pcv[cpos + t] = H.val[g.ent + t];
+        }
+        cpos += g.len;
+    }
+    out.items.push_back(d);
+    out.nnz.push_back(nnz);
+}
+
+// Cut one slab into row-range items of about C non-zeros; a row longer than
+// C becomes its own items ("pieces") combined through partial slots.
+void encode_slab(const Handle& H, uint64_t s, ChunkOut& out, Scratch& S) {
+    const uint32_t C = H.item_nnz;
+    const int64_t r0 = (int64_t)s * H.h;
+    const uint32_t nr = (uint32_t)std::min<int64_t>(H.h, H.n_rows - r0);
+    const uint64_t t0 = H.slab_tiles[s], t1 = H.slab_tiles[s + 1];
+    S.rdeg.assign(nr, 0);
+    S.cursor.resize(t1 - t0);
+    for (uint64_t t = t0; t < t1; ++t) {
+        const Tile& tl = H.tiles[t];
+        out.vt[H.variant[t]] += 1;
+        out.vn[H.variant[t]] += tl.nnz;
+        for (uint32_t i = 0; i < tl.nnz; ++i) S.rdeg[H.ent[tl.ent_begin + i] >> 16]++;
+        S.cursor[t - t0] = tl.ent_begin;
+    }
+    // gather the segments of rows [lo, hi) from every tile (cursors advance
+    // monotonically because ranges are visited in row order)
+    auto collect = [&](uint32_t lo, uint32_t hi) {
+        S.segs.clear();
+        for (uint64_t t = t0; t < t1; ++t) {
+            const Tile& tl = H.tiles[t];
+            const uint64_t end = tl.ent_begin + tl.nnz;
+            uint64_t& c = S.cursor[t - t0];
+            while (c < end && (H.ent[c] >> 16) < hi) {
+                const uint32_t r = H.ent[c] >> 16;
+                uint64_t e = c;
+                while (e < end && (H.ent[e] >> 16) == r) ++e;
+                if (r >= lo)
+                    S.segs.push_back({tl.J, r | ((uint32_t)H.variant[t] << 16), (uint32_t)(e - c), c});
+                c = e;
+            }
+        }
+    };
+    uint32_t lo = 0, running = 0;
+    bool any = false;
+    for (uint32_t r = 0; r < nr; ++r) {
+        const uint32_t dgr = S.rdeg[r];
+        if (dgr > C) {
+            if (r > lo) {
+                collect(lo, r);
+                emit_item(H, (uint32_t)s, lo, r, -1, 0, S.segs, out, S);
+            }
+            collect(r, r + 1);
+            // pieces of at most C entries; segments longer than C are cut
+            const uint32_t cid = (uint32_t)out.combine.size();
+            const uint32_t pb = out.n_parts;
+            uint32_t acc = 0;
+            S.piece.clear();
+            for (const Seg& g0 : S.segs) {
+                Seg g = g0;
+                while (g.len) {
+                    uint32_t take = std::min(g.len, C - acc);
+                    S.piece.push_back({g.J, g.row, take, g.ent});
+                    acc += take;
+                    g.len -= take;
+                    g.ent += take;
+                    if (acc == C) {
+                        emit_item(H, (uint32_t)s, r, r + 1, (int32_t)out.n_parts++, cid, S.piece, out, S);
+                        S.piece.clear();
+                        acc = 0;
+                    }
+                }
+            }
+            if (!S.piece.empty())
+                emit_item(H, (uint32_t)s, r, r + 1, (int32_t)out.n_parts++, cid, S.piece, out, S);
+            out.combine.push_back({(uint32_t)s, r, pb, out.n_parts});
+            lo = r + 1;
+            running = 0;
+            any = true;
+            continue;
+        }
+        if (running + dgr > C && r > lo) {
+            collect(lo, r);
+            emit_item(H, (uint32_t)s, lo, r, -1, 0, S.segs, out, S);
+            lo = r;
+            running = 0;
+            any = true;
+        }
+        running += dgr;
+    }
+    if (lo < nr || !any) {
+        collect(lo, nr);
+        emit_item(H, (uint32_t)s, lo, nr, -1, 0, S.segs, out, S);
     }
 }
 
@@ -374,13 +454,10 @@ spmm_status_t encode(Handle& H, std::string& err) {
     std::vector<ChunkOut> outs(nchunks);
     try {
         parallel_for(nchunks, H.threads, 1, [&](uint64_t a, uint64_t b) {
-            std::vector<uint32_t> coo_ent, coo_J;
-            std::vector<float> coo_val;
-            std::vector<Seg> lr, wr;
+            Scratch sc;
             for (uint64_t c = a; c < b; ++c) {
                 uint64_t s1 = std::min(S, (c + 1) * chunk);
-                for (uint64_t s = c * chunk; s < s1; ++s)
-                    encode_slab(H, s, outs[c], coo_ent, coo_val, coo_J, lr, wr);
+                for (uint64_t s = c * chunk; s < s1; ++s) encode_slab(H, s, outs[c], sc);
             }
         });
     } catch (const std::bad_alloc&) {
@@ -388,22 +465,23 @@ spmm_status_t encode(Handle& H, std::string& err) {
         return SPMM_ENOMEM;
     }
     Encoded E;
-    uint64_t n_items = 0, n_bytes = 0;
-    std::vector<uint64_t> item_off(nchunks + 1, 0), byte_off(nchunks + 1, 0);
+    std::vector<uint64_t> item_off(nchunks + 1, 0), byte_off(nchunks + 1, 0), comb_off(nchunks + 1, 0);
+    std::vector<uint32_t> part_off(nchunks + 1, 0);
     for (uint64_t c = 0; c < nchunks; ++c) {
         item_off[c + 1] = item_off[c] + outs[c].items.size();
         byte_off[c + 1] = byte_off[c] + outs[c].blob.size();
+        comb_off[c + 1] = comb_off[c] + outs[c].combine.size();
+        part_off[c + 1] = part_off[c] + outs[c].n_parts;
         for (int v = 0; v < SPMM_NUM_VARIANTS; ++v) {
             E.variant_tiles[v] += outs[c].vt[v];
             E.variant_nnz[v] += outs[c].vn[v];
         }
     }
-    n_items = item_off[nchunks];
-    n_bytes = byte_off[nchunks];
     try {
-        E.items.resize(n_items);
-        E.item_nnz.resize(n_items);
-        E.blob.resize(n_bytes);
+        E.items.resize(item_off[nchunks]);
+        E.item_nnz.resize(item_off[nchunks]);
+        E.blob.resize(byte_off[nchunks]);
+        E.combine.resize(comb_off[nchunks]);
     } catch (const std::bad_alloc&) {
         err = "out of host memory for the encoded tiles";
         return SPMM_ENOMEM;
@@ -415,30 +493,23 @@ spmm_status_t encode(Handle& H, std::string& err) {
             for (size_t i = 0; i < o.items.size(); ++i) {
                 ItemDesc d = o.items[i];
                 d.blob_off += byte_off[c];
+                if (d.part >= 0) {
+                    d.part += (int32_t)part_off[c];
+                    d.cid += (uint32_t)comb_off[c];
+                }
                 E.items[item_off[c] + i] = d;
                 E.item_nnz[item_off[c] + i] = o.nnz[i];
+            }
+            for (size_t i = 0; i < o.combine.size(); ++i) {
+                CombineDesc cd = o.combine[i];
+                cd.part_begin += part_off[c];
+                cd.part_end += part_off[c];
+                E.combine[comb_off[c] + i] = cd;
             }
             std::vector<uint8_t>().swap(o.blob);
         }
     });
-    // partial slots for split slabs, in item order
-    uint32_t part = 0;
-    for (uint64_t i = 0; i < n_items;) {
-        uint64_t j = i;
-        while (j < n_items && E.items[j].slab == E.items[i].slab) ++j;
-        if (j - i > 1) {
-            CombineDesc cd{E.items[i].slab, part, part + (uint32_t)(j - i), 0};
-            for (uint64_t q = i; q < j; ++q) {
-                E.items[q].part = (int32_t)part++;
-                E.items[q].cid = (uint32_t)E.combine.size();
-            }
-            E.combine.push_back(cd);
-        } else {
-            E.items[i].part = -1;
-        }
-        i = j;
-    }
-    E.n_parts = part;
+    E.n_parts = part_off[nchunks];
     H.blob_bytes = E.blob.size();
     H.enc = std::move(E);
     return SPMM_OK;
@@ -508,48 +579,84 @@ namespace spmm {
 // entries; sort them back into CSR order.
 spmm_status_t decode(const Handle& H, int64_t* row_ptr, int32_t* col, float* val,
                      std::string& err) {
+    static const uint8_t empty_payload[16] = {};
     const uint8_t* blob = H.enc.blob.empty() ? static_cast<const uint8_t*>(H.h_blob) : H.enc.blob.data();
-    if (!blob && !H.enc.items.empty()) {
+    if (!blob && H.blob_bytes == 0) blob = empty_payload;
+    if (!blob) {
         err = "no host copy of the tile payload";
         return SPMM_ESTATE;
     }
     struct Trip { int64_t r; int64_t c; float v; };
     std::vector<Trip> out;
     out.reserve((size_t)H.nnz);
+    const bool hv = H.has_val;
     for (const ItemDesc& d : H.enc.items) {
+        const ItemLayout L = item_layout(d, hv);
         const uint8_t* base = blob + d.blob_off;
         const int64_t row0 = (int64_t)d.slab * H.h;
+        const uint32_t lo = d.rows & 0xFFFFu, hi = d.rows >> 16;
+        auto check_row = [&](uint32_t r) { return r >= lo && r < hi; };
         const uint32_t* ent = reinterpret_cast<const uint32_t*>(base);
         const float* cval = reinterpret_cast<const float*>(base + 4 * (size_t)d.n_coo);
-        const uint32_t* ct = reinterpret_cast<const uint32_t*>(base + d.o_coo_tile);
-        uint32_t ord = 0;
+        const uint32_t* cJ = reinterpret_cast<const uint32_t*>(base + L.o_coo_J);
+        int64_t ord = -1;
         for (uint32_t e = 0; e < d.n_coo; ++e) {
-            while (ord + 1 < d.n_coo_tiles && ct[2 * (ord + 1) + 1] <= e) ++ord;
-            int64_t c = ((int64_t)ct[2 * ord] << H.wshift) + (ent[e] & 0xFFFFu);
-            out.push_back({row0 + (ent[e] >> 16), c, H.has_val ? cval[e] : 1.0f});
+            if (ent[e] & kCooNewTile) ++ord;
+            const uint32_t r = (ent[e] >> 16) & 0xFFFu;
+            if (ord < 0 || ord >= (int64_t)d.n_coo_J || !check_row(r)) {
+                err = "COO entry outside its item";
+                return SPMM_ESTATE;
+            }
+            int64_t c = ((int64_t)cJ[ord] << H.wshift) + (ent[e] & 0xFFFFu);
+            out.push_back({row0 + r, c, hv ? cval[e] : 1.0f});
         }
-        const uint32_t* ld = reinterpret_cast<const uint32_t*>(base + d.o_lr_desc);
-        const uint32_t* ls = reinterpret_cast<const uint32_t*>(base + d.o_lr_start);
-        const uint32_t* lj = reinterpret_cast<const uint32_t*>(base + d.o_lr_J);
-        const uint16_t* cols = reinterpret_cast<const uint16_t*>(base + d.o_cols);
-        const float* cv = reinterpret_cast<const float*>(base + d.o_col_val);
-        for (uint32_t s = 0; s < d.n_lr; ++s) {
-            int64_t cb = (int64_t)lj[ld[s] >> 16] << H.wshift;
-            for (uint32_t t = ls[s]; t < ls[s + 1]; ++t)
-                out.push_back({row0 + (ld[s] & 0xFFFFu), cb + cols[t], H.has_val ? cv[t] : 1.0f});
+        const uint32_t* ls = reinterpret_cast<const uint32_t*>(base + L.o_lr);
+        const uint32_t* lj = reinterpret_cast<const uint32_t*>(base + L.o_lr_J);
+        const uint16_t* cols = reinterpret_cast<const uint16_t*>(base + L.o_cols);
+        const float* cv = reinterpret_cast<const float*>(base + L.o_cval);
+        for (uint32_t q = 0; q < d.n_lr; ++q) {
+            const uint32_t r = ls[2 * q] & 0xFFFu, tord = ls[2 * q] >> 12;
+            const uint32_t start = ls[2 * q + 1] & ((1u << kLrStartBits) - 1), len = ls[2 * q + 1] >> kLrStartBits;
+            if (tord >= d.n_lr_J || !check_row(r) || start + 64u * (len ? len - 1 : 0) >= d.n_cols + (len ? 0 : 1)) {
+                err = "row segment outside its item";
+                return SPMM_ESTATE;
+            }
+            int64_t cb = (int64_t)lj[tord] << H.wshift;
+            for (uint32_t t = 0; t < len; ++t)
+                out.push_back({row0 + r, cb + cols[start + 64u * t], hv ? cv[start + 64u * t] : 1.0f});
         }
-        const uint32_t* wr = reinterpret_cast<const uint32_t*>(base + d.o_wr);
+        const uint32_t* wr = reinterpret_cast<const uint32_t*>(base + L.o_wr);
         for (uint32_t q = 0; q < d.n_wr; ++q) {
             const uint32_t* g = wr + 4 * q;
+            if (!check_row(g[1]) || g[2] + g[3] > d.n_cols) {
+                err = "wavefront segment outside its item";
+                return SPMM_ESTATE;
+            }
             int64_t cb = (int64_t)g[0] << H.wshift;
             for (uint32_t t = 0; t < g[3]; ++t)
-                out.push_back({row0 + g[1], cb + cols[g[2] + t], H.has_val ? cv[g[2] + t] : 1.0f});
+                out.push_back({row0 + g[1], cb + cols[g[2] + t], hv ? cv[g[2] + t] : 1.0f});
         }
     }
     if ((int64_t)out.size() != H.nnz) {
         err = "decoded entry count differs from nnz";
         return SPMM_ESTATE;
     }
+    // every row must be written by exactly one owner: an item's row range,
+    // or the combine of a split row
+    std::vector<uint8_t> own((size_t)H.n_rows, 0);
+    for (const ItemDesc& d : H.enc.items) {
+        if (d.part >= 0) continue;
+        const int64_t row0 = (int64_t)d.slab * H.h;
+        for (uint32_t r = d.rows & 0xFFFFu; r < (d.rows >> 16); ++r) own[row0 + r]++;
+    }
+    for (const CombineDesc& c : H.enc.combine) own[(int64_t)c.slab * H.h + c.row]++;
+    for (int64_t r = 0; r < H.n_rows; ++r)
+        if (own[r] != 1) {
+            err = "row " + std::to_string(r) + " has " + std::to_string(own[r]) + " owners";
+            return SPMM_ESTATE;
+        }
+    if (H.relabel)
+        for (Trip& t : out) t.c = H.col_old[(size_t)t.c];
     std::sort(out.begin(), out.end(), [](const Trip& a, const Trip& b) {
         return a.r != b.r ? a.r < b.r : a.c < b.c;
     });

@@ -1,6 +1,8 @@
 // Internal types shared by the host builder, the ABI layer and the kernels.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <cstdint>
 #include <functional>
@@ -12,9 +14,10 @@
 namespace spmm {
 
 constexpr uint32_t kMaxTileRows = 4096;
-constexpr uint32_t kDefaultTileRows = 256;
+constexpr uint32_t kDefaultTileRows = 64;
 constexpr uint32_t kDefaultTileCols = 65536;
 constexpr uint32_t kDefaultItemNnz = 16384;
+constexpr uint32_t kMaxItemNnz = 131072;
 // Rows longer than this are cut into several row segments in the ROW
 // variant, so that one lane never walks an unbounded row.
 constexpr uint32_t kRowLaneMax = 1024;
@@ -23,34 +26,59 @@ constexpr uint32_t kWaveRowMin = 64;
 // Largest column chunk one kernel launch accumulates (LDS budget).
 constexpr int kMaxKc = 32;
 
-// One work item = one wavefront.  It owns a part of one tile row (slab):
-// its LDS accumulator covers the slab's h rows.  All offsets are in bytes,
-// relative to the item's payload start in the blob.
+// One work item = one wavefront.  It owns the local rows [lo, hi) of one
+// tile row (slab) -- its LDS accumulator rows -- and all of their entries in
+// every tile of the slab, unless it is one piece of a row too long for one
+// item (then hi = lo + 1 and `part` names the partial slot it writes).
 //
-// Payload layout (16-byte aligned start):
-//   coo_ent   u32[n_coo]        (row << 16) | col, grouped by tile
-//   coo_val   f32[n_coo]        only for weighted A
-//   coo_tile  u32x2[n_coo_tiles] {strip J, first entry}, 8-byte aligned
-//   lr_desc   u32[n_lr]         row | (strip ordinal << 16)
-//   lr_start  u32[n_lr + 1]     segment extents into cols
-//   lr_J      u32[n_lr_tiles]   strip of each ordinal
-//   wr_seg    u32x4[n_wr]       {J, row, first col, length}, 16-byte aligned
-//   cols      u16[...]          columns of lr and wr segments
-//   col_val   f32[...]          only for weighted A, 4-byte aligned
+// Payload layout (byte offsets from blob_off, see item_layout):
+//   coo_ent  u32[n_coo]      bit 31: first COO entry of a new tile;
+//                            bits 16..27: local row; bits 0..15: local col
+//   coo_val  f32[n_coo]      weighted A only
+//   coo_J    u32[n_coo_J]    strip (tile column) of each COO tile run
+//   lr_seg   u32x2[n_lr]     x = row | strip ordinal << 12,
+//                            y = first col slot | length << 21   (8-aligned)
+//   lr_J     u32[n_lr_J]     strip of each ordinal
+//   wr_seg   u32x4[n_wr]     {strip, row, first col, length}     (16-aligned)
+//   cols     u16[n_cols]     row-lane segments interleaved in blocks of 64
+//                            (element t of segment i of a block at
+//                            block_base + i + 64 t), then wavefront segments
+//   col_val  f32[n_cols]     weighted A only                     (4-aligned)
 struct ItemDesc {
     uint64_t blob_off;
     uint32_t slab;
-    int32_t part;  // -1: the item owns its slab; else its partial-result slot
-    uint32_t n_coo, n_coo_tiles, n_lr, n_wr;
-    uint32_t cid;  // split slabs: index of the slab's CombineDesc (coo_val sits at 4 * n_coo)
-    uint32_t o_coo_tile, o_lr_desc, o_lr_start, o_lr_J, o_wr, o_cols, o_col_val;
+    int32_t part;  // -1: the item owns rows [lo, hi); else its partial slot
+    uint32_t rows; // lo | hi << 16
+    uint32_t cid;  // split rows: index of the row's CombineDesc
+    uint32_t n_coo, n_coo_J, n_lr, n_lr_J, n_wr, n_cols;
 };
-static_assert(sizeof(ItemDesc) == 64, "ItemDesc must stay 64 bytes");
+static_assert(sizeof(ItemDesc) == 48, "ItemDesc must stay 48 bytes");
 
-// A split slab: Y rows = sum of the partial slots [part_begin, part_end),
-// formed by whichever of its items finishes last.
+struct ItemLayout {
+    uint32_t o_coo_J, o_lr, o_lr_J, o_wr, o_cols, o_cval, bytes;
+};
+
+__host__ __device__ inline uint32_t align_to(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
+
+__host__ __device__ inline ItemLayout item_layout(const ItemDesc& d, bool has_val) {
+    ItemLayout L;
+    L.o_coo_J = 4u * d.n_coo * (has_val ? 2u : 1u);
+    L.o_lr = align_to(L.o_coo_J + 4u * d.n_coo_J, 8);
+    L.o_lr_J = L.o_lr + 8u * d.n_lr;
+    L.o_wr = align_to(L.o_lr_J + 4u * d.n_lr_J, 16);
+    L.o_cols = L.o_wr + 16u * d.n_wr;
+    L.o_cval = align_to(L.o_cols + 2u * d.n_cols, 4);
+    L.bytes = align_to(L.o_cval + (has_val ? 4u * d.n_cols : 0u), 16);
+    return L;
+}
+
+constexpr uint32_t kCooNewTile = 0x80000000u;
+constexpr uint32_t kLrStartBits = 21;  // lr_seg.y: start < 2^21, length < 2^11
+
+// A row split across several items: Y[row] = sum of the partial slots
+// [part_begin, part_end), formed by whichever piece finishes last.
 struct CombineDesc {
-    uint32_t slab, part_begin, part_end, pad;
+    uint32_t slab, row, part_begin, part_end;
 };
 
 // Canonical tile (host): entries ent[ent_begin, ent_begin + nnz) sorted by
@@ -87,6 +115,14 @@ struct Handle {
     std::vector<uint8_t> variant;      // per tile
     uint64_t sum_nnr = 0, sum_nnc = 0;
     uint64_t blob_bytes = 0;
+    // Column relabelling: tile columns are ranks by descending in-degree, so
+    // the X rows of hub columns are contiguous (cache-resident).
+    bool relabel = false;
+    std::vector<int32_t> col_new;      // new index of original column c
+    std::vector<int32_t> col_old;      // original column of new index
+    int32_t* d_col_old = nullptr;      // device copy of col_old
+    void* d_xperm = nullptr;           // X in relabelled row order
+    uint64_t xperm_bytes = 0;
     // encoded work
     Encoded enc;
     // device / pinned copies
@@ -94,7 +130,7 @@ struct Handle {
     void* h_blob = nullptr;       // pinned host blob (PLACE_PINNED_HOST)
     ItemDesc* d_items = nullptr;
     CombineDesc* d_combine = nullptr;
-    float* d_part = nullptr;      // partial results, n_parts * h * kMaxKc floats
+    float* d_part = nullptr;      // partial results of split rows, n_parts * kc floats
     uint32_t* d_count = nullptr;  // per split slab: items finished in this launch
     uint64_t part_cap = 0;
     int max_kc = 16;              // widest column chunk per launch (16 or 32)
@@ -141,6 +177,8 @@ struct RunArgs {
     uint32_t* count;             // device, n_combine counters, zero between launches
 };
 hipError_t launch_spmm(const Handle& H, const RunArgs& a);
+hipError_t launch_permute_rows(const void* X, int64_t ldx, int k, int esize, const int32_t* old_of_new,
+                               int64_t n, void* Xp, int64_t ldp, hipStream_t s);
 
 // quant_kernels.hip
 hipError_t launch_quantize(const float* X, int64_t n, int k, int64_t ldx, int dtype, void* Xq,

@@ -117,15 +117,17 @@ struct OutScale {
     }
 };
 
-template <int KC, int VW, typename XT>
+template <int KC, int VW, typename XT, bool HV>
 __global__ __launch_bounds__(256) void spmm_items(
     const ItemDesc* __restrict__ items, uint32_t n_items, const uint8_t* __restrict__ blob,
     uint64_t blob_bias, const XT* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
     float* __restrict__ part, const CombineDesc* __restrict__ combine,
     uint32_t* __restrict__ count, const float* __restrict__ yscale, uint32_t h, uint32_t wshift,
-    int64_t n_rows, int has_val) {
-    constexpr int G = KC / VW;
-    constexpr int P = 64 / G;
+    int64_t n_rows) {
+    constexpr bool has_val = HV;        // weighted A
+    constexpr int G = KC / VW;          // lanes per X row
+    constexpr int P = 64 / G;           // entries per step
+    constexpr int U = KC <= 4 ? 4 : 2;  // steps in flight per lane
     extern __shared__ float lds[];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -133,92 +135,143 @@ __global__ __launch_bounds__(256) void spmm_items(
     if (it >= n_items) return;
     float* acc = lds + (size_t)wave * h * KC;
     const ItemDesc d = items[it];
+    const ItemLayout L = item_layout(d, has_val);
     const uint8_t* base = blob + (d.blob_off - blob_bias);
+    const uint32_t lo = d.rows & 0xFFFFu, hi = d.rows >> 16;
 
-    for (uint32_t i = lane; i < h * KC; i += 64) acc[i] = 0.0f;
+    for (uint32_t i = lane; i < (hi - lo) * KC; i += 64) acc[lo * KC + i] = 0.0f;
     wave_sync();
 
     const int g = lane % G;
     const uint32_t slot = lane / G;
     const int c0 = g * VW;
+    const uint64_t le_mask = lane == 63 ? ~0ull : ((2ull << lane) - 1);
 
-    // ---- COO stream: one entry per lane group
-    {
+    // Loads inside the unrolled steps are unconditional (indices clamped to
+    // the last valid element, out-of-range slots weighted 0), so each phase
+    // issues its U loads back to back and waits once.
+
+    // ---- COO stream: one entry per lane group.  The strip of an entry is
+    // the strip of the last tile start at or before it: a ballot of the
+    // start flags gives each lane its tile ordinal without a table walk.
+    if (d.n_coo) {
         const uint32_t* ent = reinterpret_cast<const uint32_t*>(base);
         const float* cval = reinterpret_cast<const float*>(base + 4 * (size_t)d.n_coo);
-        const uint2* ctile = reinterpret_cast<const uint2*>(base + d.o_coo_tile);
-        uint32_t cur = 0;
-        for (uint32_t pb = 0; pb < d.n_coo; pb += P) {
-            const uint32_t e = pb + slot;
-            const uint32_t pe = pb + P;
-            uint32_t ord = cur;
-            for (uint32_t t = cur + 1; t < d.n_coo_tiles; ++t) {
-                const uint32_t st = ctile[t].y;
-                if (st >= pe) break;
-                if (e >= st) ord = t;
-            }
-            if (e < d.n_coo) {
-                const uint32_t en = ent[e];
-                const uint32_t J = ctile[ord].x;
-                const XT* xp = X + (((int64_t)J << wshift) + (en & 0xFFFFu)) * ldx + c0;
-                float x[VW];
-                XLd<XT, VW>::load(xp, x);
-                const float v = has_val ? cval[e] : 1.0f;
-                float* a = acc + (en >> 16) * KC + c0;
+        const uint32_t* cJ = reinterpret_cast<const uint32_t*>(base + L.o_coo_J);
+        const uint32_t last = d.n_coo - 1;
+        int32_t seen = 0;  // tile starts before the current step
+        for (uint32_t pb = 0; pb < d.n_coo; pb += P * U) {
+            uint32_t en[U];
+            float v[U];
 #pragma unroll
-                for (int i = 0; i < VW; ++i) atomicAdd(a + i, v * x[i]);
+            for (int u = 0; u < U; ++u) {
+                const uint32_t e = min(pb + u * P + slot, last);
+                en[u] = __builtin_nontemporal_load(ent + e);
+                if constexpr (has_val) v[u] = cval[e];
+                else v[u] = 1.0f;
             }
-            while (cur + 1 < d.n_coo_tiles && ctile[cur + 1].y <= pe) ++cur;
+            uint32_t J[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = pb + u * P + slot <= last;
+                const uint64_t m = __ballot(ok && g == 0 && (en[u] & kCooNewTile));
+                const int32_t ord = seen + __popcll(m & le_mask) - 1;
+                seen += __popcll(m);
+                J[u] = cJ[ord < 0 ? 0 : ord];
+            }
+            float x[U][VW];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                XLd<XT, VW>::load(X + (((int64_t)J[u] << wshift) + (en[u] & 0xFFFFu)) * ldx + c0, x[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (pb + u * P + slot <= last) {
+                    float* a = acc + ((en[u] >> 16) & 0xFFFu) * KC + c0;
+#pragma unroll
+                    for (int i = 0; i < VW; ++i) atomicAdd(a + i, v[u] * x[u][i]);
+                }
+            }
         }
     }
 
-    const uint16_t* cols = reinterpret_cast<const uint16_t*>(base + d.o_cols);
-    const float* colv = reinterpret_cast<const float*>(base + d.o_col_val);
+    const uint16_t* cols = reinterpret_cast<const uint16_t*>(base + L.o_cols);
+    const float* colv = reinterpret_cast<const float*>(base + L.o_cval);
 
-    // ---- LR stream: one row segment per lane group
-    {
-        const uint32_t* ldesc = reinterpret_cast<const uint32_t*>(base + d.o_lr_desc);
-        const uint32_t* lstart = reinterpret_cast<const uint32_t*>(base + d.o_lr_start);
-        const uint32_t* lJ = reinterpret_cast<const uint32_t*>(base + d.o_lr_J);
+    // ---- LR stream: one row segment per lane group, U elements in flight.
+    // Segments are sorted by length and interleaved in blocks of 64, so the
+    // lanes of a step read neighbouring column slots.
+    if (d.n_lr) {
+        const uint2* lseg = reinterpret_cast<const uint2*>(base + L.o_lr);
+        const uint32_t* lJ = reinterpret_cast<const uint32_t*>(base + L.o_lr_J);
         for (uint32_t pb = 0; pb < d.n_lr; pb += P) {
             const uint32_t si = pb + slot;
-            if (si < d.n_lr) {
-                const uint32_t ds = ldesc[si];
-                const uint32_t J = lJ[ds >> 16];
-                const uint32_t a = lstart[si], b = lstart[si + 1];
-                const XT* xb = X + ((int64_t)J << wshift) * ldx + c0;
-                float s[VW];
+            const bool seg_ok = si < d.n_lr;
+            const uint2 sg = lseg[seg_ok ? si : d.n_lr - 1];
+            const uint32_t len = seg_ok ? sg.y >> kLrStartBits : 0u;
+            const uint32_t start = sg.y & ((1u << kLrStartBits) - 1);
+            const uint32_t lastq = start + 64u * ((sg.y >> kLrStartBits) - 1);
+            const uint32_t J = lJ[sg.x >> 12];
+            const XT* xb = X + ((int64_t)J << wshift) * ldx + c0;
+            float s[VW];
 #pragma unroll
-                for (int i = 0; i < VW; ++i) s[i] = 0.0f;
-                for (uint32_t t = a; t < b; ++t) {
-                    float x[VW];
-                    XLd<XT, VW>::load(xb + (int64_t)cols[t] * ldx, x);
-                    const float v = has_val ? colv[t] : 1.0f;
+            for (int i = 0; i < VW; ++i) s[i] = 0.0f;
+            for (uint32_t t = 0; t < len; t += U) {
+                uint32_t cc[U];
+                float w[U];
 #pragma unroll
-                    for (int i = 0; i < VW; ++i) s[i] += v * x[i];
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t q = min(start + 64u * (t + u), lastq);
+                    cc[u] = __builtin_nontemporal_load(cols + q);
+                    float wv = 1.0f;
+                    if constexpr (has_val) wv = colv[q];
+                    w[u] = t + u < len ? wv : 0.0f;
                 }
-                float* ap = acc + (ds & 0xFFFFu) * KC + c0;
+                float x[U][VW];
+#pragma unroll
+                for (int u = 0; u < U; ++u) XLd<XT, VW>::load(xb + (int64_t)cc[u] * ldx, x[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int i = 0; i < VW; ++i) s[i] += w[u] * x[u][i];
+            }
+            if (seg_ok) {
+                float* ap = acc + (sg.x & 0xFFFu) * KC + c0;
 #pragma unroll
                 for (int i = 0; i < VW; ++i) atomicAdd(ap + i, s[i]);
             }
         }
     }
 
-    // ---- WR stream: one row segment per wavefront
+    // ---- WR stream: one row segment per wavefront; the P lane groups
+    // stride over it (U elements in flight each), then a shuffle butterfly.
     {
-        const uint4* wr = reinterpret_cast<const uint4*>(base + d.o_wr);
+        const uint4* wr = reinterpret_cast<const uint4*>(base + L.o_wr);
         for (uint32_t q = 0; q < d.n_wr; ++q) {
             const uint4 sg = wr[q];  // {J, row, first col, length}
             const XT* xb = X + ((int64_t)sg.x << wshift) * ldx + c0;
+            const uint16_t* cp = cols + sg.z;
+            const float* vp = colv + sg.z;
             float s[VW];
 #pragma unroll
             for (int i = 0; i < VW; ++i) s[i] = 0.0f;
-            for (uint32_t t = slot; t < sg.w; t += P) {
-                float x[VW];
-                XLd<XT, VW>::load(xb + (int64_t)cols[sg.z + t] * ldx, x);
-                const float v = has_val ? colv[sg.z + t] : 1.0f;
+            for (uint32_t t = slot; t < sg.w; t += P * U) {
+                uint32_t cc[U];
+                float w[U];
 #pragma unroll
-                for (int i = 0; i < VW; ++i) s[i] += v * x[i];
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t q2 = min(t + u * P, sg.w - 1);
+                    cc[u] = __builtin_nontemporal_load(cp + q2);
+                    float wv = 1.0f;
+                    if constexpr (has_val) wv = vp[q2];
+                    w[u] = t + u * P < sg.w ? wv : 0.0f;
+                }
+                float x[U][VW];
+#pragma unroll
+                for (int u = 0; u < U; ++u) XLd<XT, VW>::load(xb + (int64_t)cc[u] * ldx, x[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int i = 0; i < VW; ++i) s[i] += w[u] * x[u][i];
             }
 #pragma unroll
             for (int m = G; m < 64; m <<= 1)
@@ -234,22 +287,20 @@ __global__ __launch_bounds__(256) void spmm_items(
 
     wave_sync();
     const int64_t row0 = (int64_t)d.slab * h;
-    const int64_t left = n_rows - row0;
-    const uint32_t rows = left < (int64_t)h ? (uint32_t)left : h;
-    const uint32_t total = rows * KC;
     if (d.part < 0) {
+        const uint32_t total = (hi - lo) * KC;
+        float* yb = Y + (row0 + lo) * ldy;
         for (uint32_t i = lane; i < total; i += 64) {
             const uint32_t r = i / KC, c = i % KC;
-            Y[(row0 + r) * ldy + c] = OutScale<XT>::apply(acc[i], yscale, c);
+            yb[r * ldy + c] = OutScale<XT>::apply(acc[lo * KC + i], yscale, c);
         }
         return;
     }
-    // Split tile row: publish this item's partial sums; the last item of the
-    // tile row to finish adds all partial slots in slot order (so the result
-    // does not depend on which item finishes last), writes Y, and re-arms
-    // the counter for the next launch.
-    float* pp = part + (size_t)d.part * h * KC;
-    for (uint32_t i = lane; i < total; i += 64) pp[i] = acc[i];
+    // One piece of a split row: publish its KC partial sums; the last piece
+    // of the row to finish adds the slots in slot order (so the result does
+    // not depend on which piece finishes last), writes Y and re-arms the
+    // counter for the next launch.
+    if (lane < KC) part[(size_t)d.part * KC + lane] = acc[lo * KC + lane];
     __threadfence();
     uint32_t old = 0;
     if (lane == 0) old = atomicAdd(&count[d.cid], 1u);
@@ -257,14 +308,11 @@ __global__ __launch_bounds__(256) void spmm_items(
     const CombineDesc cd = combine[d.cid];
     if (old != cd.part_end - cd.part_begin - 1) return;
     __threadfence();
-    const float* p0 = part + (size_t)cd.part_begin * h * KC;
-    const size_t stride = (size_t)h * KC;
-    const uint32_t np = cd.part_end - cd.part_begin;
-    for (uint32_t i = lane; i < total; i += 64) {
+    if (lane < KC) {
         float s = 0.0f;
-        for (uint32_t q = 0; q < np; ++q) s += __builtin_nontemporal_load(p0 + q * stride + i);
-        const uint32_t r = i / KC, c = i % KC;
-        Y[(row0 + r) * ldy + c] = OutScale<XT>::apply(s, yscale, c);
+        for (uint32_t p = cd.part_begin; p < cd.part_end; ++p)
+            s += __builtin_nontemporal_load(part + (size_t)p * KC + lane);
+        Y[(row0 + cd.row) * ldy + lane] = OutScale<XT>::apply(s, yscale, lane);
     }
     if (lane == 0) atomicExch(&count[d.cid], 0u);
 }
@@ -272,15 +320,23 @@ __global__ __launch_bounds__(256) void spmm_items(
 template <typename XT, int KC, int VW>
 hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
                       const float* yscale) {
+    // 160 KB of LDS per CU; small accumulators pack four wavefronts per
+    // workgroup so that the per-CU workgroup limit does not cap residency.
     const uint32_t per_wave = H.h * KC * 4u;
-    uint32_t wpb = 65536u / per_wave;
-    wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
+    const uint32_t wpb = per_wave <= 8192u ? 4u : per_wave <= 32768u ? 2u : 1u;
     const uint32_t grid = (a.n_items + wpb - 1) / wpb;
-    if (grid)
-        hipLaunchKernelGGL((spmm_items<KC, VW, XT>), dim3(grid), dim3(64 * wpb),
-                           (size_t)per_wave * wpb, a.stream, a.items, a.n_items, a.blob,
-                           a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part, a.combine, a.count, yscale,
-                           H.h, H.wshift, (int64_t)H.n_rows, (int)H.has_val);
+    if (grid) {
+        if (H.has_val)
+            hipLaunchKernelGGL((spmm_items<KC, VW, XT, true>), dim3(grid), dim3(64 * wpb),
+                               (size_t)per_wave * wpb, a.stream, a.items, a.n_items, a.blob,
+                               a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part, a.combine, a.count,
+                               yscale, H.h, H.wshift, (int64_t)H.n_rows);
+        else
+            hipLaunchKernelGGL((spmm_items<KC, VW, XT, false>), dim3(grid), dim3(64 * wpb),
+                               (size_t)per_wave * wpb, a.stream, a.items, a.n_items, a.blob,
+                               a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part, a.combine, a.count,
+                               yscale, H.h, H.wshift, (int64_t)H.n_rows);
+    }
     return hipGetLastError();
 }
 
@@ -325,7 +381,40 @@ hipError_t launch_typed(const Handle& H, const RunArgs& a) {
     return hipSuccess;
 }
 
+// Xp[i, :] = X[old_of_new[i], :] (the relabelled column order).  Lanes run
+// across (row, column) pairs, so writes are coalesced and each source row is
+// read as one contiguous piece.
+template <typename T>
+__global__ __launch_bounds__(256) void permute_rows(const T* __restrict__ X, int64_t ldx, int k,
+                                                    const int32_t* __restrict__ old_of_new,
+                                                    int64_t n, T* __restrict__ Xp, int64_t ldp) {
+    const int64_t total = n * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / k;
+        const int j = (int)(t - i * k);
+        Xp[i * ldp + j] = X[(int64_t)old_of_new[i] * ldx + j];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_permute_rows(const void* X, int64_t ldx, int k, int esize, const int32_t* old_of_new,
+                               int64_t n, void* Xp, int64_t ldp, hipStream_t s) {
+    const int64_t total = n * k;
+    if (!total) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>(65536, (total + 255) / 256);
+    if (esize == 4)
+        hipLaunchKernelGGL(permute_rows<uint32_t>, dim3(blocks), dim3(256), 0, s,
+                           static_cast<const uint32_t*>(X), ldx, k, old_of_new, n, static_cast<uint32_t*>(Xp), ldp);
+    else if (esize == 2)
+        hipLaunchKernelGGL(permute_rows<uint16_t>, dim3(blocks), dim3(256), 0, s,
+                           static_cast<const uint16_t*>(X), ldx, k, old_of_new, n, static_cast<uint16_t*>(Xp), ldp);
+    else
+        hipLaunchKernelGGL(permute_rows<uint8_t>, dim3(blocks), dim3(256), 0, s,
+                           static_cast<const uint8_t*>(X), ldx, k, old_of_new, n, static_cast<uint8_t*>(Xp), ldp);
+    return hipGetLastError();
+}
 
 hipError_t launch_spmm(const Handle& H, const RunArgs& a) {
     switch (a.dtype) {

@@ -68,11 +68,12 @@ GEOMS = [dict(), dict(tile_rows=16, tile_cols=32), dict(tile_rows=1, tile_cols=1
          dict(tile_rows=100, tile_cols=256, item_nnz=64), dict(tile_rows=4096, tile_cols=65536, item_nnz=1)]
 
 
+@pytest.mark.parametrize("keep_order", [False, True])
 @pytest.mark.parametrize("geom", GEOMS)
 @pytest.mark.parametrize("variant", range(pk.SPMM_NUM_VARIANTS))
-def test_encode_decode_roundtrip(geom, variant):
+def test_encode_decode_roundtrip(geom, variant, keep_order):
     rp, col = synth.rmat_csr(11, 8, seed=3)
-    h = pk.spmm_build_tiles(rp, col, fixed_variant=variant, **geom)
+    h = pk.spmm_build_tiles(rp, col, fixed_variant=variant, keep_order=keep_order, **geom)
     drp, dcol = pk.spmm_decode_tiles(h, col.shape[0])
     assert np.array_equal(drp, rp) and np.array_equal(dcol, col)
     st = pk.spmm_get_stats(h)
@@ -118,14 +119,18 @@ def test_tile_stats_match_definition():
     rp, col = synth.rmat_csr(12, 8, seed=2)
     n = 1 << 12
     h, w = 64, 128
-    hd = pk.spmm_build_tiles(rp, col, tile_rows=h, tile_cols=w)
-    st = pk.spmm_get_stats(hd)
     rows = np.repeat(np.arange(n), np.diff(rp))
-    tiles = (rows // h) * (n // w) + col // w
-    assert st["n_tiles"] == np.unique(tiles).size
-    assert st["sum_nnr"] == np.unique(tiles * n + rows).size
-    assert st["sum_nnc"] == np.unique(tiles * n + col).size
-    hd.close()
+    indeg = np.bincount(col, minlength=n)
+    rank = np.empty(n, np.int64)
+    rank[np.lexsort((np.arange(n), -indeg))] = np.arange(n)   # by (-in-degree, id)
+    for keep, c in ((True, col.astype(np.int64)), (False, rank[col])):
+        hd = pk.spmm_build_tiles(rp, col, tile_rows=h, tile_cols=w, keep_order=keep)
+        st = pk.spmm_get_stats(hd)
+        tiles = (rows // h) * (n // w) + c // w
+        assert st["n_tiles"] == np.unique(tiles).size
+        assert st["sum_nnr"] == np.unique(tiles * n + rows).size
+        assert st["sum_nnc"] == np.unique(tiles * n + c).size
+        hd.close()
 
 
 @pytest.mark.parametrize("t", [1, 7, 64, 16384])
