@@ -99,6 +99,10 @@ typedef struct {
                                  row order (a handle-owned buffer), so the X rows
                                  of hub columns are contiguous and cache-resident;
                                  1: tiles keep the given column order             */
+    uint32_t stream_kib;     /* streamed mode: payload per host->device transfer
+                                 group, KiB; 0 -> 262144 (256 MiB)                 */
+    uint32_t ring_depth;     /* streamed mode: device slots in the transfer ring;
+                                 0 -> 3; 2..16                                    */
 } spmm_build_opts;
 
 typedef struct spmm_handle_s* spmm_handle_t;
@@ -167,6 +171,66 @@ spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_
 spmm_status_t spmm_quantize_x(const float* X, int64_t n, int k, int64_t ldx, spmm_xdtype_t dt,
                               void* Xq, int64_t ldq, float* col_scale, uint32_t flags,
                               hipStream_t s);
+
+/*
+ * Y = A X with the tile payload in pinned host memory: the semi-external
+ * mode of Section 3.1 on one GPU (A in host DRAM instead of on SSDs; X and Y
+ * resident in HBM).  Consecutive work items are grouped into transfers of
+ * about opts.stream_kib KiB; each group is copied on `copy` into one slot of a
+ * ring of opts.ring_depth device buffers while the kernels of the previous
+ * groups run on `compute` (events order each copy after the kernels that
+ * last read its slot, and each kernel after its copy).
+ *   h : built with opts.place = SPMM_PLACE_PINNED_HOST.  Other arguments as
+ *       spmm_run.  compute and copy should be different streams for overlap.
+ * The result is identical to spmm_run's on the same tiles (same kernels,
+ * same work items).  Asynchronous.  The first call allocates the ring.
+ * Errors: SPMM_EINVAL, SPMM_ESTATE (tiles placed in HBM), SPMM_ENOMEM,
+ * SPMM_EHIP.
+ */
+spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
+                              const float* col_scale, float* Y, int64_t ldy, hipStream_t compute,
+                              hipStream_t copy);
+
+/*
+ * PageRank power iteration (Section 4.1):
+ *   PR'(u) = (1 - d)/N + d * ( sum_{v in B(u)} PR(v) / L(v)  +  D/N ),
+ * B(u) = in-neighbours of u, L(v) = out-degree of v, D = sum of PR over the
+ * vertices with L = 0 (dangling mass, spread evenly so that sum PR = 1; the
+ * paper's formula without this term is SPMM_PR_NO_REDISTRIBUTE).
+ *   h      : handle of the n x n matrix whose row u lists the in-neighbours of
+ *            u, i.e. the transpose of the adjacency matrix (for an undirected
+ *            graph, the adjacency matrix itself).  L(v) is taken as the number
+ *            of entries in column v of this matrix.
+ *   pr     : device float[n]; initialised to 1/N unless SPMM_PR_INIT_GIVEN;
+ *            holds the result.
+ *   resid  : host double[iters] (or NULL): resid[t] = sum_u |PR_{t+1}(u) - PR_t(u)|,
+ *            reduced in FP64 (as is D).
+ *   flags  : SPMM_PR_INIT_GIVEN | SPMM_PR_NO_REDISTRIBUTE | SPMM_PR_NO_GRAPH
+ *            (the default captures all iterations into one HIP graph).
+ * Exactly `iters` iterations (no early stop).  Synchronous: returns after the
+ * last iteration has finished.  Errors: SPMM_EINVAL, SPMM_ESTATE, SPMM_ENOMEM,
+ * SPMM_EHIP.
+ */
+#define SPMM_PR_INIT_GIVEN 1u
+#define SPMM_PR_NO_REDISTRIBUTE 2u
+#define SPMM_PR_NO_GRAPH 4u
+spmm_status_t spmm_pagerank(spmm_handle_t h, float damping, int iters, uint32_t flags, float* pr,
+                            double* resid, hipStream_t s);
+
+/*
+ * Non-negative matrix factorisation A ~ W H^T by the multiplicative updates
+ * of Section 4.3, H first, then W, every iteration:
+ *   H <- H * (A^T W) / (H (W^T W) + eps),   W <- W * (A H) / (W (H^T H) + eps).
+ *   hA, hAT : handles of A (n x m) and of A^T (pass hA twice if A is symmetric).
+ *   rank    : r, 1..32.   W : device float n x r;  H : device float m x r (the
+ *             paper's H transposed), both row-major with stride r, updated in place.
+ *   eps     : added to every denominator (rows of isolated vertices go to 0).
+ * Gram matrices are accumulated in FP64 (deterministic order), everything
+ * else in FP32.  Synchronous.  Errors: SPMM_EINVAL, SPMM_ESTATE, SPMM_ENOMEM,
+ * SPMM_EHIP.
+ */
+spmm_status_t spmm_nmf(spmm_handle_t hA, spmm_handle_t hAT, int rank, int iters, float eps, float* W,
+                       float* H, hipStream_t s);
 
 /*
  * Rebuild the CSR of A from the encoded work items (host copy of the tile

@@ -45,7 +45,8 @@ class spmm_build_opts(ctypes.Structure):
                 ("fixed_variant", ctypes.c_int32), ("item_nnz", ctypes.c_uint32),
                 ("place", ctypes.c_uint32), ("threads", ctypes.c_uint32),
                 ("validate", ctypes.c_uint32), ("max_kc", ctypes.c_uint32),
-                ("keep_order", ctypes.c_uint32)]
+                ("keep_order", ctypes.c_uint32), ("stream_kib", ctypes.c_uint32),
+                ("ring_depth", ctypes.c_uint32)]
 
 
 class spmm_stats_t(ctypes.Structure):
@@ -87,6 +88,12 @@ def load_library():
     L.spmm_run.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp]
     L.spmm_quantize_x.restype = i32
     L.spmm_quantize_x.argtypes = [vp, i64, i32, i64, i32, vp, i64, vp, ctypes.c_uint32, vp]
+    L.spmm_stream_run.restype = i32
+    L.spmm_stream_run.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp, vp]
+    L.spmm_pagerank.restype = i32
+    L.spmm_pagerank.argtypes = [vp, ctypes.c_float, i32, ctypes.c_uint32, vp, vp, vp]
+    L.spmm_nmf.restype = i32
+    L.spmm_nmf.argtypes = [vp, vp, i32, i32, ctypes.c_float, vp, vp, vp]
     L.spmm_get_stats.restype = i32
     L.spmm_get_stats.argtypes = [vp, ctypes.POINTER(spmm_stats_t)]
     L.spmm_decode_tiles.restype = i32
@@ -166,7 +173,8 @@ class Handle:
 def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *,
                      tile_rows: int = 0, tile_cols: int = 0, fixed_variant: int = -1,
                      item_nnz: int = 0, place: int = SPMM_PLACE_DEVICE, threads: int = 0,
-                     validate: bool = True, max_kc: int = 0, keep_order: bool = False) -> Handle:
+                     validate: bool = True, max_kc: int = 0, keep_order: bool = False,
+                     stream_kib: int = 0, ring_depth: int = 0) -> Handle:
     L = load_library()
     rp = _host(row_ptr, np.int64)
     ci = _host(col_idx, np.int32)
@@ -174,7 +182,7 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
     n_rows = rp.shape[0] - 1
     n_cols = n_rows if n_cols is None else int(n_cols)
     o = spmm_build_opts(tile_rows, tile_cols, fixed_variant, item_nnz, place, threads,
-                        int(bool(validate)), max_kc, int(bool(keep_order)))
+                        int(bool(validate)), max_kc, int(bool(keep_order)), stream_kib, ring_depth)
     out = ctypes.c_void_p()
     st = L.spmm_build_tiles(n_rows, n_cols, rp.ctypes.data, None if ci is None or ci.size == 0 else ci.ctypes.data,
                             None if va is None else va.ctypes.data, ctypes.byref(o), ctypes.byref(out))
@@ -228,6 +236,37 @@ def spmm_quantize_x(X, Xq, dtype: int, col_scale=None, flags: int = 0, n: int | 
     st = L.spmm_quantize_x(_ptr(X), int(n), int(k), int(ldx), int(dtype), _ptr(Xq), int(ldq),
                            _ptr(col_scale), int(flags), _stream(stream, X))
     _check(st, "spmm_quantize_x")
+
+
+def spmm_stream_run(h: Handle, X, Y, compute=None, copy=None, k: int | None = None, ldx: int | None = None,
+                    dtype: int | None = None, col_scale=None, ldy: int | None = None):
+    """Y = A X with A streamed from pinned host memory (see spmm.h)."""
+    L = load_library()
+    k = X.shape[1] if k is None else k
+    ldx = X.stride(0) if ldx is None else ldx
+    ldy = Y.stride(0) if ldy is None else ldy
+    st = L.spmm_stream_run(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
+                           int(ldy), _stream(compute, X), _stream(copy))
+    _check(st, "spmm_stream_run")
+
+
+SPMM_PR_INIT_GIVEN, SPMM_PR_NO_REDISTRIBUTE, SPMM_PR_NO_GRAPH = 1, 2, 4
+
+
+def spmm_pagerank(h: Handle, pr, iters: int = 30, damping: float = 0.85, flags: int = 0, stream=None):
+    """PageRank on the device; returns the FP64 residual per iteration."""
+    resid = np.zeros(max(iters, 1), dtype=np.float64)
+    st = load_library().spmm_pagerank(h.ptr, float(damping), int(iters), int(flags), _ptr(pr),
+                                      resid.ctypes.data, _stream(stream, pr))
+    _check(st, "spmm_pagerank")
+    return resid[:iters]
+
+
+def spmm_nmf(hA: Handle, hAT: Handle, W, H, iters: int = 10, eps: float = 1e-9, stream=None):
+    """NMF multiplicative updates on the device (W: n x r, H: m x r, in place)."""
+    st = load_library().spmm_nmf(hA.ptr, hAT.ptr, int(W.shape[1]), int(iters), float(eps), _ptr(W), _ptr(H),
+                                 _stream(stream, W))
+    _check(st, "spmm_nmf")
 
 
 def spmm_get_stats(h: Handle) -> dict:

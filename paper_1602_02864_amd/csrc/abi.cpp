@@ -35,11 +35,19 @@ void free_device(spmm::Handle& H) {
     if (H.d_part) hipFree(H.d_part);
     if (H.d_count) hipFree(H.d_count);
     if (H.d_col_old) hipFree(H.d_col_old);
+    if (H.d_col_count) hipFree(H.d_col_count);
+    H.d_col_count = nullptr;
     if (H.d_xperm) hipFree(H.d_xperm);
     H.d_col_old = nullptr;
     H.d_xperm = nullptr;
     H.xperm_bytes = 0;
     if (H.h_blob) hipHostFree(H.h_blob);
+    for (void* q : H.ring) hipFree(q);
+    for (hipEvent_t e : H.ev_ready) hipEventDestroy(e);
+    for (hipEvent_t e : H.ev_free) hipEventDestroy(e);
+    H.ring.clear();
+    H.ev_ready.clear();
+    H.ev_free.clear();
     H.d_blob = H.h_blob = nullptr;
     H.d_items = nullptr;
     H.d_combine = nullptr;
@@ -64,6 +72,19 @@ spmm_status_t upload(spmm::Handle& H) {
         if ((e = hipHostMalloc(&H.h_blob, nb, hipHostMallocDefault)) != hipSuccess)
             return fail(SPMM_ENOMEM, "hipHostMalloc(tile payload) failed");
         if (E.blob.size()) std::memcpy(H.h_blob, E.blob.data(), E.blob.size());
+        // consecutive items whose payload adds up to about stream_bytes form
+        // one transfer group (items are laid out back to back in the blob)
+        H.groups.clear();
+        const uint64_t ni = E.items.size();
+        uint64_t i0 = 0;
+        while (i0 < ni) {
+            const uint64_t b0 = E.items[i0].blob_off;
+            uint64_t i1 = i0 + 1;
+            while (i1 < ni && E.items[i1].blob_off - b0 < H.stream_bytes) ++i1;
+            const uint64_t b1 = i1 < ni ? E.items[i1].blob_off : (uint64_t)E.blob.size();
+            H.groups.push_back({i0, i1, b0, b1});
+            i0 = i1;
+        }
     }
     const size_t ni = E.items.size() ? E.items.size() : 1;
     if ((e = hipMalloc(&H.d_items, ni * sizeof(spmm::ItemDesc))) != hipSuccess)
@@ -125,6 +146,75 @@ spmm_status_t check_run_args(const spmm::Handle& H, const void* X, int k, int64_
     return SPMM_OK;
 }
 
+spmm_status_t prepare_device(spmm::Handle& H) {
+    spmm_status_t st = ensure_uploaded(H);
+    if (st != SPMM_OK) return st;
+    return ensure_partials(H);
+}
+
+spmm_status_t ensure_xperm(spmm::Handle& H, uint64_t need) {
+    if (need <= H.xperm_bytes) return SPMM_OK;
+    if (H.d_xperm) hipFree(H.d_xperm);
+    H.d_xperm = nullptr;
+    H.xperm_bytes = 0;
+    if (hipMalloc(&H.d_xperm, need) != hipSuccess) return fail(SPMM_ENOMEM, "hipMalloc(relabelled X) failed");
+    H.xperm_bytes = need;
+    return SPMM_OK;
+}
+
+// Enqueue Y = A X on s over the device-resident payload.  With
+// x_in_handle_order the rows of X are already in the handle's column order;
+// otherwise (and if the handle relabels columns) X is first gathered into a
+// handle-owned buffer in that order.  Buffers must already exist when this
+// runs under stream capture (it allocates only when X needs gathering).
+spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt, const float* col_scale,
+                         float* Y, int64_t ldy, hipStream_t s, bool x_in_handle_order) {
+    spmm::RunArgs a{};
+    a.X = X;
+    a.k = k;
+    a.ldx = ldx;
+    if (H.relabel && H.n_cols > 0 && !x_in_handle_order) {
+        const int esize = dt == SPMM_X_F32 ? 4 : dt == SPMM_X_BF16 ? 2 : 1;
+        const int64_t ldp = (k + 3) / 4 * 4;
+        spmm_status_t st = ensure_xperm(H, (uint64_t)H.n_cols * ldp * esize);
+        if (st != SPMM_OK) return st;
+        hipError_t pe = spmm::launch_permute_rows(X, ldx, k, esize, H.d_col_old, H.n_cols, H.d_xperm, ldp, s);
+        if (pe != hipSuccess) return hip_fail(pe, "X permutation launch");
+        a.X = H.d_xperm;
+        a.ldx = ldp;
+    }
+    a.dtype = dt;
+    a.col_scale = col_scale;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.stream = s;
+    a.blob = static_cast<const uint8_t*>(H.d_blob);
+    a.blob_bias = 0;
+    a.items = H.d_items;
+    a.n_items = (uint32_t)H.enc.items.size();
+    a.combine = H.d_combine;
+    a.n_combine = (uint32_t)H.enc.combine.size();
+    a.count = H.d_count;
+    hipError_t e = spmm::launch_spmm(H, a);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SPMM_OK;
+}
+
+// Scoped device buffers for the application drivers.
+struct DevBufs {
+    std::vector<void*> p;
+    ~DevBufs() {
+        for (void* q : p) hipFree(q);
+    }
+    template <typename T>
+    T* get(size_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+        p.push_back(q);
+        return static_cast<T*>(q);
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -165,6 +255,9 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         H.place = o.place;
         H.max_kc = (int)o.max_kc;
         H.relabel = o.keep_order == 0;
+        H.stream_bytes = (uint64_t)(o.stream_kib ? o.stream_kib : 262144u) << 10;
+        H.ring_depth = o.ring_depth ? o.ring_depth : 3u;
+        if (H.ring_depth < 2 || H.ring_depth > 16) return fail(SPMM_EINVAL, "ring_depth must be in 2..16");
         std::string err;
         spmm_status_t st = spmm::build_canonical(H, row_ptr, col_idx, values, o.validate != 0, err);
         if (st != SPMM_OK) return fail(st, err);
@@ -195,26 +288,48 @@ spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_
         spmm_status_t st = check_run_args(H, X, k, ldx, dt, col_scale, Y, ldy);
         if (st != SPMM_OK) return st;
         if (H.n_rows == 0) return SPMM_OK;
-        if ((st = ensure_uploaded(H)) != SPMM_OK) return st;
-        if ((st = ensure_partials(H)) != SPMM_OK) return st;
+        if ((st = prepare_device(H)) != SPMM_OK) return st;
+        return run_device(H, X, k, ldx, dt, col_scale, Y, ldy, s, false);
+    } catch (const std::exception& e) {
+        return fail(SPMM_EINVAL, e.what());
+    }
+}
+
+spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
+                              const float* col_scale, float* Y, int64_t ldy, hipStream_t compute,
+                              hipStream_t copy) {
+    try {
+        if (!h) return fail(SPMM_EINVAL, "handle is NULL");
+        spmm::Handle& H = h->H;
+        if (H.place != SPMM_PLACE_PINNED_HOST)
+            return fail(SPMM_ESTATE, "tiles are placed in HBM; build with place = SPMM_PLACE_PINNED_HOST");
+        spmm_status_t st = check_run_args(H, X, k, ldx, dt, col_scale, Y, ldy);
+        if (st != SPMM_OK) return st;
+        if (H.n_rows == 0) return SPMM_OK;
+        if ((st = prepare_device(H)) != SPMM_OK) return st;
+        if (H.ring.empty()) {
+            uint64_t slot = 16;
+            for (const auto& g : H.groups) slot = std::max(slot, g.b1 - g.b0);
+            for (uint32_t r = 0; r < H.ring_depth; ++r) {
+                void* q = nullptr;
+                if (hipMalloc(&q, slot) != hipSuccess) return fail(SPMM_ENOMEM, "hipMalloc(stream ring) failed");
+                H.ring.push_back(q);
+                hipEvent_t a, b;
+                hipEventCreateWithFlags(&a, hipEventDisableTiming);
+                hipEventCreateWithFlags(&b, hipEventDisableTiming);
+                H.ev_ready.push_back(a);
+                H.ev_free.push_back(b);
+            }
+        }
         spmm::RunArgs a{};
         a.X = X;
         a.k = k;
         a.ldx = ldx;
         if (H.relabel && H.n_cols > 0) {
-            // gather X into the relabelled row order, rows padded to 4 elements
             const int esize = dt == SPMM_X_F32 ? 4 : dt == SPMM_X_BF16 ? 2 : 1;
             const int64_t ldp = (k + 3) / 4 * 4;
-            const uint64_t need = (uint64_t)H.n_cols * ldp * esize;
-            if (need > H.xperm_bytes) {
-                if (H.d_xperm) hipFree(H.d_xperm);
-                H.d_xperm = nullptr;
-                H.xperm_bytes = 0;
-                if (hipMalloc(&H.d_xperm, need) != hipSuccess)
-                    return fail(SPMM_ENOMEM, "hipMalloc(relabelled X) failed");
-                H.xperm_bytes = need;
-            }
-            hipError_t pe = spmm::launch_permute_rows(X, ldx, k, esize, H.d_col_old, H.n_cols, H.d_xperm, ldp, s);
+            if ((st = ensure_xperm(H, (uint64_t)H.n_cols * ldp * esize)) != SPMM_OK) return st;
+            hipError_t pe = spmm::launch_permute_rows(X, ldx, k, esize, H.d_col_old, H.n_cols, H.d_xperm, ldp, compute);
             if (pe != hipSuccess) return hip_fail(pe, "X permutation launch");
             a.X = H.d_xperm;
             a.ldx = ldp;
@@ -223,19 +338,157 @@ spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_
         a.col_scale = col_scale;
         a.Y = Y;
         a.ldy = ldy;
-        a.stream = s;
-        a.blob = static_cast<const uint8_t*>(H.d_blob);
-        a.blob_bias = 0;
-        a.items = H.d_items;
-        a.n_items = (uint32_t)H.enc.items.size();
+        a.stream = compute;
         a.combine = H.d_combine;
         a.n_combine = (uint32_t)H.enc.combine.size();
         a.count = H.d_count;
-        hipError_t e = spmm::launch_spmm(H, a);
-        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        const uint32_t R = (uint32_t)H.ring.size();
+        for (size_t g = 0; g < H.groups.size(); ++g) {
+            const auto& G = H.groups[g];
+            const uint32_t slot = (uint32_t)(g % R);
+            hipError_t e;
+            // the copy into a slot waits until the kernels reading its
+            // previous group are done; the kernels wait for their copy
+            if (g >= R && (e = hipStreamWaitEvent(copy, H.ev_free[slot], 0)) != hipSuccess) return hip_fail(e, "wait");
+            if ((e = hipMemcpyAsync(H.ring[slot], static_cast<uint8_t*>(H.h_blob) + G.b0, G.b1 - G.b0,
+                                    hipMemcpyHostToDevice, copy)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(tile group)");
+            if ((e = hipEventRecord(H.ev_ready[slot], copy)) != hipSuccess) return hip_fail(e, "record");
+            if ((e = hipStreamWaitEvent(compute, H.ev_ready[slot], 0)) != hipSuccess) return hip_fail(e, "wait");
+            a.blob = static_cast<const uint8_t*>(H.ring[slot]);
+            a.blob_bias = G.b0;
+            a.items = H.d_items + G.i0;
+            a.n_items = (uint32_t)(G.i1 - G.i0);
+            if ((e = spmm::launch_spmm(H, a)) != hipSuccess) return hip_fail(e, "kernel launch");
+            if ((e = hipEventRecord(H.ev_free[slot], compute)) != hipSuccess) return hip_fail(e, "record");
+        }
         return SPMM_OK;
-    } catch (const std::exception& e) {
-        return fail(SPMM_EINVAL, e.what());
+    } catch (const std::exception& ex) {
+        return fail(SPMM_EINVAL, ex.what());
+    }
+}
+
+spmm_status_t spmm_pagerank(spmm_handle_t h, float damping, int iters, uint32_t flags, float* pr,
+                            double* resid, hipStream_t s) {
+    try {
+        if (!h || !pr) return fail(SPMM_EINVAL, "NULL argument");
+        spmm::Handle& H = h->H;
+        if (H.n_rows != H.n_cols) return fail(SPMM_EINVAL, "PageRank needs a square matrix");
+        if (iters < 0 || !(damping >= 0.0f && damping <= 1.0f)) return fail(SPMM_EINVAL, "bad damping or iters");
+        if (flags & ~(SPMM_PR_INIT_GIVEN | SPMM_PR_NO_REDISTRIBUTE | SPMM_PR_NO_GRAPH))
+            return fail(SPMM_EINVAL, "unknown flags");
+        if (H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "tiles are placed in host memory");
+        const int64_t n = H.n_rows;
+        if (n == 0) return SPMM_OK;
+        spmm_status_t st = prepare_device(H);
+        if (st != SPMM_OK) return st;
+        hipError_t e;
+        if (!H.d_col_count) {
+            if (hipMalloc(&H.d_col_count, sizeof(uint32_t) * (size_t)n) != hipSuccess)
+                return fail(SPMM_ENOMEM, "hipMalloc(out-degrees) failed");
+            if ((e = hipMemcpy(H.d_col_count, H.col_count.data(), sizeof(uint32_t) * (size_t)n,
+                               hipMemcpyHostToDevice)) != hipSuccess)
+                return hip_fail(e, "hipMemcpy(out-degrees)");
+        }
+        DevBufs B;
+        float* xp = B.get<float>((size_t)n);
+        float* y = B.get<float>((size_t)n);
+        double* dpart = B.get<double>(1024);
+        double* rpart = B.get<double>(1024);
+        double* D = B.get<double>(1);
+        double* dres = B.get<double>((size_t)std::max(iters, 1));
+        if (!xp || !y || !dpart || !rpart || !D || !dres) return fail(SPMM_ENOMEM, "hipMalloc(PageRank workspace) failed");
+        hipStream_t cs = nullptr;
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        hipEvent_t ev = nullptr;
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        hipEventRecord(ev, s);
+        hipStreamWaitEvent(cs, ev, 0);
+        if (!(flags & SPMM_PR_INIT_GIVEN)) spmm::launch_pr_init(pr, n, (float)(1.0 / (double)n), cs);
+        const int redistribute = (flags & SPMM_PR_NO_REDISTRIBUTE) ? 0 : 1;
+        const int32_t* perm = H.relabel ? H.d_col_old : nullptr;
+        auto enqueue = [&]() -> spmm_status_t {
+            for (int it = 0; it < iters; ++it) {
+                hipError_t pe = spmm::launch_pr_prepare(pr, H.d_col_count, perm, n, xp, dpart, D, cs);
+                if (pe != hipSuccess) return hip_fail(pe, "PageRank prepare launch");
+                spmm_status_t rs = run_device(H, xp, 1, 1, SPMM_X_F32, nullptr, y, 1, cs, true);
+                if (rs != SPMM_OK) return rs;
+                pe = spmm::launch_pr_update(pr, y, n, (double)damping, D, redistribute, rpart, dres + it, cs);
+                if (pe != hipSuccess) return hip_fail(pe, "PageRank update launch");
+            }
+            return SPMM_OK;
+        };
+        spmm_status_t rs = SPMM_OK;
+        if (flags & SPMM_PR_NO_GRAPH) {
+            rs = enqueue();
+        } else {
+            // all iterations as one HIP graph
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+                rs = hip_fail(e, "hipStreamBeginCapture");
+            } else {
+                rs = enqueue();
+                hipError_t ce = hipStreamEndCapture(cs, &graph);
+                if (rs == SPMM_OK && ce != hipSuccess) rs = hip_fail(ce, "hipStreamEndCapture");
+                if (rs == SPMM_OK && (e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+                    rs = hip_fail(e, "hipGraphInstantiate");
+                if (rs == SPMM_OK && (e = hipGraphLaunch(exec, cs)) != hipSuccess) rs = hip_fail(e, "hipGraphLaunch");
+            }
+            if (rs == SPMM_OK) hipStreamSynchronize(cs);
+            if (exec) hipGraphExecDestroy(exec);
+            if (graph) hipGraphDestroy(graph);
+        }
+        if (rs == SPMM_OK && resid && iters > 0)
+            if ((e = hipMemcpyAsync(resid, dres, sizeof(double) * (size_t)iters, hipMemcpyDeviceToHost, cs)) != hipSuccess)
+                rs = hip_fail(e, "hipMemcpy(residuals)");
+        hipError_t se = hipStreamSynchronize(cs);
+        if (rs == SPMM_OK && se != hipSuccess) rs = hip_fail(se, "PageRank execution");
+        hipEventDestroy(ev);
+        hipStreamDestroy(cs);
+        return rs;
+    } catch (const std::exception& ex) {
+        return fail(SPMM_EINVAL, ex.what());
+    }
+}
+
+spmm_status_t spmm_nmf(spmm_handle_t hA, spmm_handle_t hAT, int rank, int iters, float eps, float* W, float* Hm,
+                       hipStream_t s) {
+    try {
+        if (!hA || !hAT || !W || !Hm) return fail(SPMM_EINVAL, "NULL argument");
+        spmm::Handle& A = hA->H;
+        spmm::Handle& AT = hAT->H;
+        if (rank < 1 || rank > 32) return fail(SPMM_EINVAL, "rank must be in 1..32");
+        if (iters < 0 || !(eps >= 0.0f)) return fail(SPMM_EINVAL, "bad iters or eps");
+        if (AT.n_rows != A.n_cols || AT.n_cols != A.n_rows)
+            return fail(SPMM_EINVAL, "hAT must hold the transpose of hA (the same handle if A is symmetric)");
+        if (A.place != SPMM_PLACE_DEVICE || AT.place != SPMM_PLACE_DEVICE)
+            return fail(SPMM_ESTATE, "tiles are placed in host memory");
+        const int64_t n = A.n_rows, m = A.n_cols;
+        spmm_status_t st = prepare_device(A);
+        if (st == SPMM_OK && hAT != hA) st = prepare_device(AT);
+        if (st != SPMM_OK) return st;
+        DevBufs B;
+        float* S = B.get<float>((size_t)std::max(n, m) * rank);
+        double* part = B.get<double>((size_t)spmm::gram_blocks() * rank * rank);
+        float* G = B.get<float>((size_t)rank * rank);
+        if (!S || !part || !G) return fail(SPMM_ENOMEM, "hipMalloc(NMF workspace) failed");
+        hipError_t e;
+        for (int it = 0; it < iters; ++it) {
+            // H <- H * (A^T W) / (H (W^T W) + eps)
+            if ((e = spmm::launch_gram(W, n, rank, part, G, s)) != hipSuccess) return hip_fail(e, "Gram launch");
+            if ((st = run_device(AT, W, rank, rank, SPMM_X_F32, nullptr, S, rank, s, false)) != SPMM_OK) return st;
+            if ((e = spmm::launch_mu_update(Hm, S, G, m, rank, eps, s)) != hipSuccess) return hip_fail(e, "update launch");
+            // W <- W * (A H) / (W (H^T H) + eps)
+            if ((e = spmm::launch_gram(Hm, m, rank, part, G, s)) != hipSuccess) return hip_fail(e, "Gram launch");
+            if ((st = run_device(A, Hm, rank, rank, SPMM_X_F32, nullptr, S, rank, s, false)) != SPMM_OK) return st;
+            if ((e = spmm::launch_mu_update(W, S, G, n, rank, eps, s)) != hipSuccess) return hip_fail(e, "update launch");
+        }
+        // the workspace is freed on return: finish the work that uses it
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "NMF execution");
+        return SPMM_OK;
+    } catch (const std::exception& ex) {
+        return fail(SPMM_EINVAL, ex.what());
     }
 }
 

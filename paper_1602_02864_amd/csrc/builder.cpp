@@ -88,13 +88,14 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
     // Column relabelling by descending in-degree (ties by column id): a
     // counting sort over degrees, stable in the original order.
     const int32_t* cmap = nullptr;
+    H.col_count.assign((size_t)H.n_cols, 0);
+    std::vector<uint32_t>& indeg = H.col_count;
+    parallel_for((uint64_t)n, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
+        for (int64_t p = row_ptr[a]; p < row_ptr[b]; ++p)
+            __atomic_fetch_add(&indeg[col[p]], 1u, __ATOMIC_RELAXED);
+    });
     if (H.relabel) {
         const int64_t m = H.n_cols;
-        std::vector<uint32_t> indeg((size_t)m, 0);
-        parallel_for((uint64_t)n, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
-            for (int64_t p = row_ptr[a]; p < row_ptr[b]; ++p)
-                __atomic_fetch_add(&indeg[col[p]], 1u, __ATOMIC_RELAXED);
-        });
         uint32_t maxd = 0;
         for (int64_t c = 0; c < m; ++c) maxd = std::max(maxd, indeg[c]);
         std::vector<uint64_t> start((size_t)maxd + 2, 0);

@@ -121,6 +121,8 @@ struct Handle {
     std::vector<int32_t> col_new;      // new index of original column c
     std::vector<int32_t> col_old;      // original column of new index
     int32_t* d_col_old = nullptr;      // device copy of col_old
+    std::vector<uint32_t> col_count;   // entries per original column
+    uint32_t* d_col_count = nullptr;   // device copy (PageRank out-degrees)
     void* d_xperm = nullptr;           // X in relabelled row order
     uint64_t xperm_bytes = 0;
     // encoded work
@@ -134,6 +136,16 @@ struct Handle {
     uint32_t* d_count = nullptr;  // per split slab: items finished in this launch
     uint64_t part_cap = 0;
     int max_kc = 16;              // widest column chunk per launch (16 or 32)
+    // streamed mode: item groups copied host -> device ring per SpMM
+    struct Group {
+        uint64_t i0, i1;          // items
+        uint64_t b0, b1;          // payload bytes
+    };
+    std::vector<Group> groups;
+    uint64_t stream_bytes = 0;
+    uint32_t ring_depth = 0;
+    std::vector<void*> ring;      // device slots, each max group bytes
+    std::vector<hipEvent_t> ev_ready, ev_free;
     int device = 0;
     bool uploaded = false;
 };
@@ -179,6 +191,16 @@ struct RunArgs {
 hipError_t launch_spmm(const Handle& H, const RunArgs& a);
 hipError_t launch_permute_rows(const void* X, int64_t ldx, int k, int esize, const int32_t* old_of_new,
                                int64_t n, void* Xp, int64_t ldp, hipStream_t s);
+
+// apps_kernels.hip
+hipError_t launch_pr_init(float* pr, int64_t n, float v, hipStream_t s);
+hipError_t launch_pr_prepare(const float* pr, const uint32_t* outdeg, const int32_t* old_of_new, int64_t n,
+                             float* xp, double* dpart, double* D, hipStream_t s);
+hipError_t launch_pr_update(float* pr, const float* y, int64_t n, double damping, const double* D,
+                            int redistribute, double* rpart, double* resid_slot, hipStream_t s);
+int gram_blocks();
+hipError_t launch_gram(const float* M, int64_t n, int r, double* part, float* G, hipStream_t s);
+hipError_t launch_mu_update(float* M, const float* S, const float* G, int64_t n, int r, float eps, hipStream_t s);
 
 // quant_kernels.hip
 hipError_t launch_quantize(const float* X, int64_t n, int k, int64_t ldx, int dtype, void* Xq,
