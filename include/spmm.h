@@ -57,11 +57,14 @@ typedef enum {
  * 16-bit row and column indices local to the tile (Section 3.2).  Every
  * variant computes the same product; they differ in how the tile's entries
  * are encoded and mapped onto the 64 lanes of a wavefront:
- *   COO    - every entry as a (row, col) pair, one lane (group) per entry.
+ *   COO    - every entry as a (row, col) pair, one lane (group) per entry,
+ *            pairs in column order inside the tile, so that lanes gathering
+ *            the same X row share one memory request.
  *   ROW    - rows with one entry as COO pairs, the other rows in the
  *            paper's SCSR+COO layout (Section 3.2): one lane (group) per row.
- *   HYBRID - as ROW, but rows of 64 or more entries are given a whole
- *            wavefront, which splits the row and reduces it with shuffles.
+ *   HYBRID - rows shorter than 64 entries as COO pairs, longer rows on a
+ *            whole wavefront, which splits the row and reduces it with
+ *            cross-lane shuffles (the default).
  *   WAVE   - single-entry rows as COO, every other row one wavefront.
  */
 typedef enum {

@@ -34,6 +34,10 @@ void free_device(spmm::Handle& H) {
     if (H.d_combine) hipFree(H.d_combine);
     if (H.d_part) hipFree(H.d_part);
     if (H.d_count) hipFree(H.d_count);
+    if (H.d_colmax) hipFree(H.d_colmax);
+    if (H.d_fexp) hipFree(H.d_fexp);
+    H.d_colmax = nullptr;
+    H.d_fexp = nullptr;
     if (H.d_col_old) hipFree(H.d_col_old);
     if (H.d_col_count) hipFree(H.d_col_count);
     H.d_col_count = nullptr;
@@ -81,6 +85,12 @@ spmm_status_t upload(spmm::Handle& H) {
             const uint64_t b0 = E.items[i0].blob_off;
             uint64_t i1 = i0 + 1;
             while (i1 < ni && E.items[i1].blob_off - b0 < H.stream_bytes) ++i1;
+            // never split the pieces of one split row across groups: each
+            // launch must see all pieces of a row, so that its per-row
+            // counter and partial slots are used by one column chunk at a time
+            while (i1 < ni && E.items[i1].part >= 0 && E.items[i1 - 1].part >= 0 &&
+                   E.items[i1].cid == E.items[i1 - 1].cid)
+                ++i1;
             const uint64_t b1 = i1 < ni ? E.items[i1].blob_off : (uint64_t)E.blob.size();
             H.groups.push_back({i0, i1, b0, b1});
             i0 = i1;
@@ -100,6 +110,9 @@ spmm_status_t upload(spmm::Handle& H) {
         return hip_fail(e, "hipMemcpy(combine list)");
     if ((e = hipMalloc(&H.d_count, nc * sizeof(uint32_t))) != hipSuccess)
         return fail(SPMM_ENOMEM, "hipMalloc(combine counters) failed");
+    if (hipMalloc(&H.d_colmax, 64 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&H.d_fexp, 64 * sizeof(int32_t)) != hipSuccess)
+        return fail(SPMM_ENOMEM, "hipMalloc(fixed-point scales) failed");
     if ((e = hipMemset(H.d_count, 0, nc * sizeof(uint32_t))) != hipSuccess)
         return hip_fail(e, "hipMemset(combine counters)");
     if (H.relabel && H.n_cols > 0) {
@@ -123,12 +136,12 @@ spmm_status_t ensure_uploaded(spmm::Handle& H) {
 }
 
 spmm_status_t ensure_partials(spmm::Handle& H) {
-    const uint64_t need = H.enc.n_parts * (uint64_t)spmm::kc_cap(H);
+    const uint64_t need = H.enc.n_parts * (uint64_t)spmm::kc_cap(H);  // int64 slots
     if (need == 0 || need <= H.part_cap) return SPMM_OK;
     if (H.d_part) hipFree(H.d_part);
     H.d_part = nullptr;
     H.part_cap = 0;
-    if (hipMalloc(&H.d_part, need * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&H.d_part, need * sizeof(int64_t)) != hipSuccess)
         return fail(SPMM_ENOMEM, "hipMalloc(partial results) failed");
     H.part_cap = need;
     return SPMM_OK;
@@ -188,6 +201,12 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
     a.Y = Y;
     a.ldy = ldy;
     a.stream = s;
+    {
+        hipError_t fe = spmm::launch_fixed_exponents(a.X, dt, H.n_cols, k, a.ldx, H.max_row_l1, H.d_colmax,
+                                                     H.d_fexp, s);
+        if (fe != hipSuccess) return hip_fail(fe, "fixed-point scale launch");
+    }
+    a.fexp = H.d_fexp;
     a.blob = static_cast<const uint8_t*>(H.d_blob);
     a.blob_bias = 0;
     a.items = H.d_items;
@@ -339,6 +358,12 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
         a.Y = Y;
         a.ldy = ldy;
         a.stream = compute;
+        {
+            hipError_t fe = spmm::launch_fixed_exponents(a.X, dt, H.n_cols, k, a.ldx, H.max_row_l1, H.d_colmax,
+                                                         H.d_fexp, compute);
+            if (fe != hipSuccess) return hip_fail(fe, "fixed-point scale launch");
+        }
+        a.fexp = H.d_fexp;
         a.combine = H.d_combine;
         a.n_combine = (uint32_t)H.enc.combine.size();
         a.count = H.d_count;

@@ -85,6 +85,32 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
         return SPMM_EINVAL;
     }
 
+    // largest row L1 norm (bounds every partial sum of a row)
+    {
+        std::atomic<uint64_t> best{0};
+        parallel_for((uint64_t)n, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
+            double m = 0.0;
+            for (uint64_t i = a; i < b; ++i) {
+                double r = 0.0;
+                if (val)
+                    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) r += std::fabs((double)val[p]);
+                else
+                    r = (double)(row_ptr[i + 1] - row_ptr[i]);
+                m = std::max(m, r);
+            }
+            uint64_t bits;
+            std::memcpy(&bits, &m, 8);
+            uint64_t cur = best.load();
+            while (bits > cur && !best.compare_exchange_weak(cur, bits)) {}
+        });
+        uint64_t bits = best.load();
+        std::memcpy(&H.max_row_l1, &bits, 8);
+        if (!std::isfinite(H.max_row_l1)) {
+            err = "values must be finite";
+            return SPMM_EINVAL;
+        }
+    }
+
     // Column relabelling by descending in-degree (ties by column id): a
     // counting sort over degrees, stable in the original order.
     const int32_t* cmap = nullptr;
@@ -250,7 +276,13 @@ struct ChunkOut {
     uint64_t vt[SPMM_NUM_VARIANTS] = {}, vn[SPMM_NUM_VARIANTS] = {};
 };
 
+struct CooEnt {
+    uint32_t J, e;   // strip, (row << 16) | col
+    uint64_t src;    // canonical entry (for the value)
+};
+
 struct Scratch {
+    std::vector<CooEnt> coo;
     std::vector<uint32_t> rdeg;
     std::vector<uint64_t> cursor;
     std::vector<Seg> segs, lr, wr, piece;
@@ -268,32 +300,43 @@ void emit_item(const Handle& H, uint32_t slab, uint32_t lo, uint32_t hi, int32_t
     S.coo_J.clear();
     S.lr.clear();
     S.wr.clear();
+    S.coo.clear();
     uint32_t nnz = 0;
     for (const Seg& g : segs) {
         nnz += g.len;
         const int v = g.row >> 16;  // the tile's variant rides in the high bits
         const uint32_t row = g.row & 0xFFFFu;
-        if (v == SPMM_VAR_COO || g.len == 1) {
-            bool first = S.coo_J.empty() || S.coo_J.back() != g.J;
-            if (first) S.coo_J.push_back(g.J);
-            for (uint32_t q = 0; q < g.len; ++q) {
-                uint32_t e = H.ent[g.ent + q];
-                S.coo_ent.push_back((first && q == 0 ? kCooNewTile : 0u) | e);
-                if (hv) S.coo_val.push_back(H.val[g.ent + q]);
-            }
-        } else if (v == SPMM_VAR_ROW || (v == SPMM_VAR_HYBRID && g.len < kWaveRowMin)) {
+        const bool coo = v == SPMM_VAR_COO || g.len == 1 || (v == SPMM_VAR_HYBRID && g.len < kWaveRowMin);
+        if (coo) {
+            for (uint32_t q = 0; q < g.len; ++q) S.coo.push_back({g.J, H.ent[g.ent + q], g.ent + q});
+        } else if (v == SPMM_VAR_ROW) {
             for (uint32_t q = 0; q < g.len; q += kRowLaneMax)
                 S.lr.push_back({g.J, row, std::min(kRowLaneMax, g.len - q), g.ent + q});
         } else {
             S.wr.push_back({g.J, row, g.len, g.ent});
         }
     }
+    // COO entries in column-major order inside each tile, so that lanes of
+    // one step gathering the same (or a neighbouring) X row share its cache
+    // line.  (Accumulation is exact integer arithmetic, so any order gives
+    // the same result.)
+    std::sort(S.coo.begin(), S.coo.end(), [](const CooEnt& a, const CooEnt& b) {
+        if (a.J != b.J) return a.J < b.J;
+        const uint32_t ca = a.e & 0xFFFFu, cb = b.e & 0xFFFFu;
+        return ca != cb ? ca < cb : a.e < b.e;
+    });
+    for (size_t q = 0; q < S.coo.size(); ++q) {
+        const bool first = q == 0 || S.coo[q].J != S.coo[q - 1].J;
+        if (first) S.coo_J.push_back(S.coo[q].J);
+        S.coo_ent.push_back((first ? kCooNewTile : 0u) | S.coo[q].e);
+        if (hv) S.coo_val.push_back(H.val[S.coo[q].src]);
+    }
+    // row-lane segments: longest first, interleaved in blocks of 64
     std::stable_sort(S.lr.begin(), S.lr.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
     S.Js.clear();
     for (const Seg& g : S.lr) S.Js.push_back(g.J);
     std::sort(S.Js.begin(), S.Js.end());
     S.Js.erase(std::unique(S.Js.begin(), S.Js.end()), S.Js.end());
-    // interleaved row-lane columns: blocks of 64 segments, stride 64
     uint32_t lr_cols = 0;
     for (size_t b = 0; b < S.lr.size(); b += 64) lr_cols += 64u * S.lr[b].len;
     uint32_t wr_cols = 0;

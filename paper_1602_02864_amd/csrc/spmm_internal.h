@@ -32,8 +32,9 @@ constexpr int kMaxKc = 32;
 // item (then hi = lo + 1 and `part` names the partial slot it writes).
 //
 // Payload layout (byte offsets from blob_off, see item_layout):
-//   coo_ent  u32[n_coo]      bit 31: first COO entry of a new tile;
-//                            bits 16..27: local row; bits 0..15: local col
+//   coo_ent  u32[n_coo]      bit 31: first entry of a new strip run;
+//                            bits 16..27: local row; bits 0..15: local col;
+//                            column-major order inside each strip run
 //   coo_val  f32[n_coo]      weighted A only
 //   coo_J    u32[n_coo_J]    strip (tile column) of each COO tile run
 //   lr_seg   u32x2[n_lr]     x = row | strip ordinal << 12,
@@ -115,6 +116,9 @@ struct Handle {
     std::vector<uint8_t> variant;      // per tile
     uint64_t sum_nnr = 0, sum_nnc = 0;
     uint64_t blob_bytes = 0;
+    double max_row_l1 = 0.0;           // max over rows of sum |a_ij|
+    uint32_t* d_colmax = nullptr;      // per X column: max |x| (FP32 bits)
+    int32_t* d_fexp = nullptr;         // per X column: fixed-point exponent
     // Column relabelling: tile columns are ranks by descending in-degree, so
     // the X rows of hub columns are contiguous (cache-resident).
     bool relabel = false;
@@ -132,7 +136,7 @@ struct Handle {
     void* h_blob = nullptr;       // pinned host blob (PLACE_PINNED_HOST)
     ItemDesc* d_items = nullptr;
     CombineDesc* d_combine = nullptr;
-    float* d_part = nullptr;      // partial results of split rows, n_parts * kc floats
+    int64_t* d_part = nullptr;    // partial results of split rows, n_parts * kc fixed-point
     uint32_t* d_count = nullptr;  // per split slab: items finished in this launch
     uint64_t part_cap = 0;
     int max_kc = 16;              // widest column chunk per launch (16 or 32)
@@ -150,11 +154,16 @@ struct Handle {
     bool uploaded = false;
 };
 
-// Widest column chunk whose per-wavefront accumulator (h x kc FP32) fits
+// Widest column chunk whose per-wavefront accumulator (h x kc int64) fits
 // in 64 KB of LDS, bounded by the handle's max_kc.
+// Strip-table entries of an item's COO stream staged in LDS per wavefront.
+constexpr uint32_t kJTab = 256;
+
+// Columns per launch: a wavefront's 64-bit accumulators for h rows plus its
+// strip table fit in 64 KiB of LDS.
 inline int kc_cap(const Handle& H) {
     int cap = H.max_kc;
-    while (cap > 1 && (uint64_t)H.h * cap * 4u > 65536u) cap >>= 1;
+    while (cap > 1 && (uint64_t)H.h * cap * 8u + kJTab * 4u > 65536u) cap >>= 1;
     return cap;
 }
 
@@ -187,8 +196,14 @@ struct RunArgs {
     const CombineDesc* combine;  // device
     uint32_t n_combine;
     uint32_t* count;             // device, n_combine counters, zero between launches
+    const int32_t* fexp;         // device, per column of X: fixed-point exponent
 };
 hipError_t launch_spmm(const Handle& H, const RunArgs& a);
+// Per-column fixed-point exponents for the accumulators: with M_j = max |x_j|
+// and R = max row L1 norm of A, f_j = 61 - e_j where R M_j < 2^e_j, so every
+// partial sum of a row, scaled by 2^f_j, stays below 2^61 in magnitude.
+hipError_t launch_fixed_exponents(const void* X, int dtype, int64_t n, int k, int64_t ldx, double row_l1,
+                                  uint32_t* colmax, int32_t* fexp, hipStream_t s);
 hipError_t launch_permute_rows(const void* X, int64_t ldx, int k, int esize, const int32_t* old_of_new,
                                int64_t n, void* Xp, int64_t ldp, hipStream_t s);
 

@@ -16,8 +16,14 @@
 //          sums in registers, then adds once into acc[row].
 //   WR   - one row segment per wavefront: the P lane groups stride over the
 //          segment, then a butterfly of cross-lane shuffles sums them.
-// Accumulator updates are LDS atomic adds (ds_add_f32): rows repeat across
-// tiles and segments, and only one wavefront ever touches an accumulator.
+// Accumulators are 64-bit fixed point, updated with integer LDS atomics
+// (ds_add_u64): float LDS atomics are an order of magnitude slower on this
+// hardware, and integer sums are exact and independent of the order in which
+// lanes, segments or split-row pieces arrive, so the result is
+// deterministic.  Column j is scaled by 2^f_j, chosen per call from
+// max |X[:, j]| and the largest row L1 norm of A so that no partial sum of a
+// row can exceed 2^61; each FP32 product (or FP32 register partial sum of a
+// row segment) is rounded once to the fixed-point grid.
 //
 // Tile rows with more non-zeros than one item holds are split; every piece
 // writes its accumulator to a partial slot and the last piece to finish sums
@@ -117,34 +123,47 @@ struct OutScale {
     }
 };
 
+// FP32 value -> signed 64-bit fixed point with 2^f = scale (round to
+// nearest); two's complement wraps correctly under unsigned atomic adds.
+__device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
+    return (unsigned long long)__double2ll_rn((double)v * scale);
+}
+__device__ __forceinline__ float from_fixed(unsigned long long q, int32_t f) {
+    return (float)ldexp((double)(long long)q, -f);
+}
+
 template <int KC, int VW, typename XT, bool HV>
 __global__ __launch_bounds__(256) void spmm_items(
     const ItemDesc* __restrict__ items, uint32_t n_items, const uint8_t* __restrict__ blob,
     uint64_t blob_bias, const XT* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
-    float* __restrict__ part, const CombineDesc* __restrict__ combine,
-    uint32_t* __restrict__ count, const float* __restrict__ yscale, uint32_t h, uint32_t wshift,
-    int64_t n_rows) {
+    int64_t* __restrict__ part, const CombineDesc* __restrict__ combine,
+    uint32_t* __restrict__ count, const float* __restrict__ yscale, const int32_t* __restrict__ fexp,
+    uint32_t h, uint32_t wshift, int64_t n_rows) {
     constexpr bool has_val = HV;        // weighted A
     constexpr int G = KC / VW;          // lanes per X row
     constexpr int P = 64 / G;           // entries per step
-    constexpr int U = KC <= 4 ? 4 : 2;  // steps in flight per lane
-    extern __shared__ float lds[];
+    constexpr int U = KC <= 2 ? 8 : KC <= 4 ? 4 : 2;  // steps in flight per lane
+    extern __shared__ unsigned long long lds[];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const uint32_t it = blockIdx.x * (blockDim.x >> 6) + wave;
     if (it >= n_items) return;
-    float* acc = lds + (size_t)wave * h * KC;
+    unsigned long long* acc = lds + (size_t)wave * h * KC;
     const ItemDesc d = items[it];
     const ItemLayout L = item_layout(d, has_val);
     const uint8_t* base = blob + (d.blob_off - blob_bias);
     const uint32_t lo = d.rows & 0xFFFFu, hi = d.rows >> 16;
 
-    for (uint32_t i = lane; i < (hi - lo) * KC; i += 64) acc[lo * KC + i] = 0.0f;
+    for (uint32_t i = lane; i < (hi - lo) * KC; i += 64) acc[lo * KC + i] = 0ull;
     wave_sync();
 
     const int g = lane % G;
     const uint32_t slot = lane / G;
     const int c0 = g * VW;
+    // fixed-point scale of each of this lane's columns
+    double fs[VW];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) fs[i] = ldexp(1.0, fexp[c0 + i]);
     const uint64_t le_mask = lane == 63 ? ~0ull : ((2ull << lane) - 1);
 
     // Loads inside the unrolled steps are unconditional (indices clamped to
@@ -152,32 +171,53 @@ __global__ __launch_bounds__(256) void spmm_items(
     // issues its U loads back to back and waits once.
 
     // ---- COO stream: one entry per lane group.  The strip of an entry is
-    // the strip of the last tile start at or before it: a ballot of the
-    // start flags gives each lane its tile ordinal without a table walk.
+    // the strip of the last run start at or before it: a ballot of the start
+    // flags gives each lane its run ordinal, and the item's strip table sits
+    // in LDS.  The entries of the next batch are loaded while the current
+    // batch gathers X, so each batch waits for one memory round trip.
     if (d.n_coo) {
         const uint32_t* ent = reinterpret_cast<const uint32_t*>(base);
         const float* cval = reinterpret_cast<const float*>(base + 4 * (size_t)d.n_coo);
-        const uint32_t* cJ = reinterpret_cast<const uint32_t*>(base + L.o_coo_J);
+        const uint32_t* cJg = reinterpret_cast<const uint32_t*>(base + L.o_coo_J);
+        uint32_t* jt = reinterpret_cast<uint32_t*>(lds + (size_t)(blockDim.x >> 6) * h * KC) + wave * kJTab;
+        const bool jt_lds = d.n_coo_J <= kJTab;
+        if (jt_lds) {
+            for (uint32_t i = lane; i < d.n_coo_J; i += 64) jt[i] = cJg[i];
+            wave_sync();
+        }
         const uint32_t last = d.n_coo - 1;
-        int32_t seen = 0;  // tile starts before the current step
-        for (uint32_t pb = 0; pb < d.n_coo; pb += P * U) {
-            uint32_t en[U];
-            float v[U];
+        int32_t seen = 0;  // run starts before the current step
+        uint32_t en[U];
+        float v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t e = min(pb + u * P + slot, last);
-                en[u] = __builtin_nontemporal_load(ent + e);
-                if constexpr (has_val) v[u] = cval[e];
-                else v[u] = 1.0f;
+        for (int u = 0; u < U; ++u) {
+            const uint32_t e = min((uint32_t)(u * P) + slot, last);
+            en[u] = __builtin_nontemporal_load(ent + e);
+            if constexpr (has_val) v[u] = cval[e];
+            else v[u] = 1.0f;
+        }
+        for (uint32_t pb = 0; pb < d.n_coo; pb += P * U) {
+            uint32_t enN[U];
+            float vN[U];
+            const uint32_t nb = pb + P * U;
+            if (nb < d.n_coo) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t e = min(nb + u * P + slot, last);
+                    enN[u] = __builtin_nontemporal_load(ent + e);
+                    if constexpr (has_val) vN[u] = cval[e];
+                    else vN[u] = 1.0f;
+                }
             }
             uint32_t J[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool ok = pb + u * P + slot <= last;
                 const uint64_t m = __ballot(ok && g == 0 && (en[u] & kCooNewTile));
-                const int32_t ord = seen + __popcll(m & le_mask) - 1;
+                int32_t ord = seen + __popcll(m & le_mask) - 1;
                 seen += __popcll(m);
-                J[u] = cJ[ord < 0 ? 0 : ord];
+                ord = ord < 0 ? 0 : ord;
+                J[u] = jt_lds ? jt[ord] : cJg[ord];
             }
             float x[U][VW];
 #pragma unroll
@@ -186,10 +226,15 @@ __global__ __launch_bounds__(256) void spmm_items(
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (pb + u * P + slot <= last) {
-                    float* a = acc + ((en[u] >> 16) & 0xFFFu) * KC + c0;
+                    unsigned long long* a = acc + ((en[u] >> 16) & 0xFFFu) * KC + c0;
 #pragma unroll
-                    for (int i = 0; i < VW; ++i) atomicAdd(a + i, v[u] * x[u][i]);
+                    for (int i = 0; i < VW; ++i) atomicAdd(a + i, to_fixed(v[u] * x[u][i], fs[i]));
                 }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                en[u] = enN[u];
+                v[u] = vN[u];
             }
         }
     }
@@ -234,20 +279,27 @@ __global__ __launch_bounds__(256) void spmm_items(
 #pragma unroll
                     for (int i = 0; i < VW; ++i) s[i] += w[u] * x[u][i];
             }
-            if (seg_ok) {
-                float* ap = acc + (sg.x & 0xFFFu) * KC + c0;
+            if (len) {
+                unsigned long long* ap = acc + (sg.x & 0xFFFu) * KC + c0;
 #pragma unroll
-                for (int i = 0; i < VW; ++i) atomicAdd(ap + i, s[i]);
+                for (int i = 0; i < VW; ++i) atomicAdd(ap + i, to_fixed(s[i], fs[i]));
             }
         }
     }
 
     // ---- WR stream: one row segment per wavefront; the P lane groups
     // stride over it (U elements in flight each), then a shuffle butterfly.
+    // Segment descriptors are loaded 64 at a time into lanes and broadcast.
     {
         const uint4* wr = reinterpret_cast<const uint4*>(base + L.o_wr);
+        uint4 mine = make_uint4(0u, 0u, 0u, 0u);
         for (uint32_t q = 0; q < d.n_wr; ++q) {
-            const uint4 sg = wr[q];  // {J, row, first col, length}
+            if ((q & 63) == 0 && q + lane < d.n_wr) mine = wr[q + lane];
+            uint4 sg;  // {J, row, first col, length}
+            sg.x = __shfl(mine.x, q & 63);
+            sg.y = __shfl(mine.y, q & 63);
+            sg.z = __shfl(mine.z, q & 63);
+            sg.w = __shfl(mine.w, q & 63);
             const XT* xb = X + ((int64_t)sg.x << wshift) * ldx + c0;
             const uint16_t* cp = cols + sg.z;
             const float* vp = colv + sg.z;
@@ -278,9 +330,9 @@ __global__ __launch_bounds__(256) void spmm_items(
 #pragma unroll
                 for (int i = 0; i < VW; ++i) s[i] += __shfl_xor(s[i], m);
             if (slot == 0) {
-                float* ap = acc + sg.y * KC + c0;
+                unsigned long long* ap = acc + sg.y * KC + c0;
 #pragma unroll
-                for (int i = 0; i < VW; ++i) atomicAdd(ap + i, s[i]);
+                for (int i = 0; i < VW; ++i) atomicAdd(ap + i, to_fixed(s[i], fs[i]));
             }
         }
     }
@@ -292,15 +344,15 @@ __global__ __launch_bounds__(256) void spmm_items(
         float* yb = Y + (row0 + lo) * ldy;
         for (uint32_t i = lane; i < total; i += 64) {
             const uint32_t r = i / KC, c = i % KC;
-            yb[r * ldy + c] = OutScale<XT>::apply(acc[lo * KC + i], yscale, c);
+            yb[r * ldy + c] = OutScale<XT>::apply(from_fixed(acc[lo * KC + i], fexp[c]), yscale, c);
         }
         return;
     }
-    // One piece of a split row: publish its KC partial sums; the last piece
-    // of the row to finish adds the slots in slot order (so the result does
-    // not depend on which piece finishes last), writes Y and re-arms the
-    // counter for the next launch.
-    if (lane < KC) part[(size_t)d.part * KC + lane] = acc[lo * KC + lane];
+    // One piece of a split row: publish its KC fixed-point partial sums; the
+    // last piece of the row to finish adds the slots (exact integer sums, so
+    // the result does not depend on which piece finishes last), writes Y and
+    // re-arms the counter for the next launch.
+    if (lane < KC) part[(size_t)d.part * KC + lane] = (int64_t)acc[lo * KC + lane];
     __threadfence();
     uint32_t old = 0;
     if (lane == 0) old = atomicAdd(&count[d.cid], 1u);
@@ -309,47 +361,92 @@ __global__ __launch_bounds__(256) void spmm_items(
     if (old != cd.part_end - cd.part_begin - 1) return;
     __threadfence();
     if (lane < KC) {
-        float s = 0.0f;
+        unsigned long long s = 0ull;
         for (uint32_t p = cd.part_begin; p < cd.part_end; ++p)
-            s += __builtin_nontemporal_load(part + (size_t)p * KC + lane);
-        Y[(row0 + cd.row) * ldy + lane] = OutScale<XT>::apply(s, yscale, lane);
+            s += (unsigned long long)__builtin_nontemporal_load(part + (size_t)p * KC + lane);
+        Y[(row0 + cd.row) * ldy + lane] = OutScale<XT>::apply(from_fixed(s, fexp[lane]), yscale, lane);
     }
     if (lane == 0) atomicExch(&count[d.cid], 0u);
 }
 
+// Column absmax of X as stored (decoded to FP32; |x| compared as FP32 bits).
+template <typename XT>
+__global__ __launch_bounds__(256) void colmax_kernel(const XT* __restrict__ X, int64_t n, int k, int64_t ldx,
+                                                     uint32_t* __restrict__ m) {
+    __shared__ uint32_t red[64];
+    const int per_block = (256 / k) * k;
+    if (threadIdx.x < 64) red[threadIdx.x] = 0u;
+    __syncthreads();
+    if ((int)threadIdx.x < per_block) {
+        const int j = threadIdx.x % k;
+        uint32_t best = 0u;
+        const int64_t rows_per_step = (int64_t)gridDim.x * (per_block / k);
+        for (int64_t i = (int64_t)blockIdx.x * (per_block / k) + threadIdx.x / k; i < n; i += rows_per_step) {
+            float v[1];
+            XLd<XT, 1>::load(X + i * ldx + j, v);
+            const uint32_t b = __float_as_uint(v[0]) & 0x7FFFFFFFu;
+            best = b > best ? b : best;
+        }
+        atomicMax(&red[j], best);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < k) atomicMax(&m[threadIdx.x], red[threadIdx.x]);
+}
+
+__global__ void colmax_init_kernel(uint32_t* m) {
+    if (threadIdx.x < 64) m[threadIdx.x] = 0u;
+}
+
+// f_j = 61 - e with row_l1 * M_j < 2^e (0 when the bound is 0 or not finite).
+__global__ void fexp_kernel(const uint32_t* __restrict__ m, int k, double row_l1, int32_t* __restrict__ f) {
+    const int j = threadIdx.x;
+    if (j < 64) {
+        int fj = 0;
+        if (j < k) {
+            const double b = row_l1 * (double)__uint_as_float(m[j]);
+            if (b > 0.0 && b < 1.0e300) {
+                int e;
+                (void)frexp(b, &e);
+                fj = 61 - e;
+            }
+        }
+        f[j] = fj;
+    }
+}
+
 template <typename XT, int KC, int VW>
 hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
-                      const float* yscale) {
+                      const float* yscale, const int32_t* fexp) {
     // 160 KB of LDS per CU; small accumulators pack four wavefronts per
     // workgroup so that the per-CU workgroup limit does not cap residency.
-    const uint32_t per_wave = H.h * KC * 4u;
-    const uint32_t wpb = per_wave <= 8192u ? 4u : per_wave <= 32768u ? 2u : 1u;
+    const uint32_t per_wave = H.h * KC * 8u + kJTab * 4u;
+    const uint32_t wpb = per_wave <= 12288u ? 4u : per_wave <= 34816u ? 2u : 1u;
     const uint32_t grid = (a.n_items + wpb - 1) / wpb;
     if (grid) {
         if (H.has_val)
             hipLaunchKernelGGL((spmm_items<KC, VW, XT, true>), dim3(grid), dim3(64 * wpb),
                                (size_t)per_wave * wpb, a.stream, a.items, a.n_items, a.blob,
                                a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part, a.combine, a.count,
-                               yscale, H.h, H.wshift, (int64_t)H.n_rows);
+                               yscale, fexp, H.h, H.wshift, (int64_t)H.n_rows);
         else
             hipLaunchKernelGGL((spmm_items<KC, VW, XT, false>), dim3(grid), dim3(64 * wpb),
                                (size_t)per_wave * wpb, a.stream, a.items, a.n_items, a.blob,
                                a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part, a.combine, a.count,
-                               yscale, H.h, H.wshift, (int64_t)H.n_rows);
+                               yscale, fexp, H.h, H.wshift, (int64_t)H.n_rows);
     }
     return hipGetLastError();
 }
 
 template <typename XT, int KC>
 hipError_t launch_vw(const Handle& H, const RunArgs& a, const XT* X, float* Y,
-                     const float* yscale, int vw) {
+                     const float* yscale, const int32_t* fexp, int vw) {
     if constexpr (KC >= 4) {
-        if (vw == 4) return launch_one<XT, KC, 4>(H, a, X, Y, yscale);
+        if (vw == 4) return launch_one<XT, KC, 4>(H, a, X, Y, yscale, fexp);
     }
     if constexpr (KC >= 2) {
-        if (vw == 2) return launch_one<XT, KC, 2>(H, a, X, Y, yscale);
+        if (vw == 2) return launch_one<XT, KC, 2>(H, a, X, Y, yscale, fexp);
     }
-    return launch_one<XT, KC, 1>(H, a, X, Y, yscale);
+    return launch_one<XT, KC, 1>(H, a, X, Y, yscale, fexp);
 }
 
 template <typename XT>
@@ -366,14 +463,15 @@ hipError_t launch_typed(const Handle& H, const RunArgs& a) {
         const XT* Xc = X + c0;
         float* Yc = a.Y + c0;
         const float* sc = a.col_scale ? a.col_scale + c0 : nullptr;
+        const int32_t* fx = a.fexp + c0;
         hipError_t e;
         switch (kc) {
-            case 32: e = launch_vw<XT, 32>(H, a, Xc, Yc, sc, vw); break;
-            case 16: e = launch_vw<XT, 16>(H, a, Xc, Yc, sc, vw); break;
-            case 8: e = launch_vw<XT, 8>(H, a, Xc, Yc, sc, vw); break;
-            case 4: e = launch_vw<XT, 4>(H, a, Xc, Yc, sc, vw); break;
-            case 2: e = launch_vw<XT, 2>(H, a, Xc, Yc, sc, vw); break;
-            default: e = launch_vw<XT, 1>(H, a, Xc, Yc, sc, vw); break;
+            case 32: e = launch_vw<XT, 32>(H, a, Xc, Yc, sc, fx, vw); break;
+            case 16: e = launch_vw<XT, 16>(H, a, Xc, Yc, sc, fx, vw); break;
+            case 8: e = launch_vw<XT, 8>(H, a, Xc, Yc, sc, fx, vw); break;
+            case 4: e = launch_vw<XT, 4>(H, a, Xc, Yc, sc, fx, vw); break;
+            case 2: e = launch_vw<XT, 2>(H, a, Xc, Yc, sc, fx, vw); break;
+            default: e = launch_vw<XT, 1>(H, a, Xc, Yc, sc, fx, vw); break;
         }
         if (e != hipSuccess) return e;
         c0 += kc;
@@ -398,6 +496,25 @@ __global__ __launch_bounds__(256) void permute_rows(const T* __restrict__ X, int
 }
 
 }  // namespace
+
+hipError_t launch_fixed_exponents(const void* X, int dtype, int64_t n, int k, int64_t ldx, double row_l1,
+                                  uint32_t* colmax, int32_t* fexp, hipStream_t s) {
+    hipLaunchKernelGGL(colmax_init_kernel, dim3(1), dim3(64), 0, s, colmax);
+    if (n > 0) {
+        const unsigned blocks = (unsigned)std::min<int64_t>(2048, (n + 3) / 4);
+        if (dtype == SPMM_X_BF16)
+            hipLaunchKernelGGL(colmax_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s,
+                               static_cast<const uint16_t*>(X), n, k, ldx, colmax);
+        else if (dtype == SPMM_X_FP8_E4M3)
+            hipLaunchKernelGGL(colmax_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s,
+                               static_cast<const uint8_t*>(X), n, k, ldx, colmax);
+        else
+            hipLaunchKernelGGL(colmax_kernel<float>, dim3(blocks), dim3(256), 0, s,
+                               static_cast<const float*>(X), n, k, ldx, colmax);
+    }
+    hipLaunchKernelGGL(fexp_kernel, dim3(1), dim3(64), 0, s, colmax, k, row_l1, fexp);
+    return hipGetLastError();
+}
 
 hipError_t launch_permute_rows(const void* X, int64_t ldx, int k, int esize, const int32_t* old_of_new,
                                int64_t n, void* Xp, int64_t ldp, hipStream_t s) {
