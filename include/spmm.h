@@ -273,6 +273,151 @@ spmm_status_t spmm_model_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
                                const int32_t* col_idx, int64_t t, uint64_t* n_tiles,
                                uint64_t* sum_nnr, uint64_t* sum_nnc);
 
+/* ------------------------------------------------------------------------
+ * Per-tile variant selection.
+ *
+ * The paper fixes one per-tile layout, SCSR plus COO (Section 3.2).  Here
+ * each tile picks one of the SPMM_NUM_VARIANTS encodings, either by timing
+ * (an exhaustive autotuner over buckets of similar tiles) or by a learned
+ * cost model: an MLP mapping the 8 tile features to a predicted log time
+ * per variant, the tile taking the variant of least prediction.  Tiles are
+ * numbered in the handle's order (tile rows, then strips), 0..n_tiles-1.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Features of every tile, feat[t * 8 + i] (host float[n_tiles * 8]):
+ *   0 log2(1 + nnz_t)      1 log2(1 + non-empty rows)
+ *   2 log2(1 + non-empty columns)   3 log2(1 + longest row)
+ *   4 fraction of non-empty rows with one entry
+ *   5 log2(longest row / mean row length)
+ *   6 log2(k)              7 log2(bytes per X element of dt)
+ * Errors: SPMM_EINVAL (NULL, k outside 1..64, unknown dt).
+ */
+spmm_status_t spmm_tile_features(spmm_handle_t h, int k, spmm_xdtype_t dt, float* feat);
+
+/* Current variant of every tile (host uint8[n_tiles]). */
+spmm_status_t spmm_get_variants(spmm_handle_t h, uint8_t* variant);
+
+/*
+ * Set the variant of every tile (host uint8[n_tiles], values <
+ * SPMM_NUM_VARIANTS) and re-encode the work items on the host.  Device or
+ * pinned copies are released and rebuilt by the next call that needs them,
+ * so no work on the handle may be in flight.  The matrix is unchanged.
+ * Errors: SPMM_EINVAL (NULL, a value out of range), SPMM_ENOMEM.
+ */
+spmm_status_t spmm_set_variants(spmm_handle_t h, const uint8_t* variant);
+
+/* Largest number of buckets spmm_selector_collect forms. */
+#define SPMM_MAX_BUCKETS 128
+
+typedef struct {
+    uint32_t min_tiles;  /* smallest bucket, in tiles; 0 -> 64                */
+    uint32_t reps;       /* timed launches per (bucket, variant); 0 -> 5      */
+} spmm_tune_opts;
+
+/*
+ * Bucketed timing (device placement only).  Tiles are bucketed by features
+ * 0, 4 and 5 (size, single-entry fraction, skew); neighbouring feature
+ * cells merge until each bucket holds at least min_tiles tiles.  For every
+ * bucket and variant, a matrix made of that bucket's tiles alone, all in
+ * that variant, is encoded, uploaded and multiplied by an n_cols x k X of
+ * type dt (library-owned, zero-filled: timing does not depend on values);
+ * the median launch time over reps launches, divided by the bucket's tile
+ * count, is the time per tile.  Synchronous on s.
+ *   bucket   : host uint32[n_tiles] (output): bucket of each tile
+ *   n_buckets: (output) number of buckets, <= SPMM_MAX_BUCKETS
+ *   ns       : host float[SPMM_MAX_BUCKETS * SPMM_NUM_VARIANTS] (output):
+ *              ns[b * SPMM_NUM_VARIANTS + v], nanoseconds per tile
+ * The handle's own variants and device copies are not touched.
+ * Errors: SPMM_EINVAL, SPMM_ESTATE (pinned placement), SPMM_ENOMEM, SPMM_EHIP.
+ */
+spmm_status_t spmm_selector_collect(spmm_handle_t h, int k, spmm_xdtype_t dt, const spmm_tune_opts* opts,
+                                    uint32_t* bucket, uint32_t* n_buckets, float* ns, hipStream_t s);
+
+/*
+ * Exhaustive autotuner: spmm_selector_collect, then every tile takes the
+ * variant of least time in its bucket (the lowest index on ties), then
+ * spmm_set_variants.  ns (host float[SPMM_MAX_BUCKETS * SPMM_NUM_VARIANTS]
+ * or NULL) receives the timing table, n_buckets (or NULL) its row count.
+ */
+spmm_status_t spmm_autotune(spmm_handle_t h, int k, spmm_xdtype_t dt, const spmm_tune_opts* opts,
+                            uint32_t* n_buckets, float* ns, hipStream_t s);
+
+/*
+ * The cost model: an MLP 8 -> 64 -> 64 -> SPMM_NUM_VARIANTS with ReLU after
+ * the two hidden layers, FP32.  Its parameters are one float array of
+ * SPMM_MLP_PARAMS values, each weight matrix row-major [fan_in][fan_out]
+ * (out = in . W + b):  W1 [8][64], b1 [64], W2 [64][64], b2 [64],
+ * W3 [64][V], b3 [V], at the offsets below.
+ */
+#define SPMM_MLP_HIDDEN 64
+#define SPMM_MLP_OFF_W1 0
+#define SPMM_MLP_OFF_B1 (SPMM_MLP_OFF_W1 + SPMM_NUM_FEATURES * SPMM_MLP_HIDDEN)
+#define SPMM_MLP_OFF_W2 (SPMM_MLP_OFF_B1 + SPMM_MLP_HIDDEN)
+#define SPMM_MLP_OFF_B2 (SPMM_MLP_OFF_W2 + SPMM_MLP_HIDDEN * SPMM_MLP_HIDDEN)
+#define SPMM_MLP_OFF_W3 (SPMM_MLP_OFF_B2 + SPMM_MLP_HIDDEN)
+#define SPMM_MLP_OFF_B3 (SPMM_MLP_OFF_W3 + SPMM_MLP_HIDDEN * SPMM_NUM_VARIANTS)
+#define SPMM_MLP_PARAMS (SPMM_MLP_OFF_B3 + SPMM_NUM_VARIANTS)
+
+/*
+ * He-uniform initial weights, W ~ U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)),
+ * zero biases, from SplitMix64 draws keyed by seed (host float[PARAMS]).
+ */
+spmm_status_t spmm_mlp_init(uint64_t seed, float* params);
+
+/*
+ * Inference on the device: out[i * V + v] = predicted log time of variant v
+ * for feature row i, choice[i] = argmin_v (lowest index on ties).
+ *   params: device float[PARAMS]; feat: device float[n * 8];
+ *   out: device float[n * V] or NULL; choice: device uint8[n] or NULL.
+ * Asynchronous on s.
+ */
+spmm_status_t spmm_mlp_predict(const float* params, const float* feat, int64_t n, float* out,
+                               uint8_t* choice, hipStream_t s);
+
+/*
+ * Loss and gradient on the device.  L = sum_{i,v} m_iv (out_iv - y_iv)^2 /
+ * max(1, sum m), m = mask (uint8, non-zero = measured) or all ones when
+ * mask is NULL.  grad: device float[PARAMS] (dL/dparams, same layout);
+ * loss: device double[1] or NULL.  Reductions run in a fixed order.  The
+ * call allocates its workspace and synchronises s before returning.
+ */
+spmm_status_t spmm_mlp_grad(const float* params, const float* feat, const float* target, const uint8_t* mask,
+                            int64_t n, float* grad, double* loss, hipStream_t s);
+
+/*
+ * One Adam step (Kingma and Ba, 2015) on device arrays of PARAMS floats:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t >= 1.
+ */
+spmm_status_t spmm_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t t, float lr,
+                            float beta1, float beta2, float eps, hipStream_t s);
+
+typedef struct {
+    uint32_t epochs;  /* 0 -> 30                                              */
+    uint32_t batch;   /* minibatch rows; 0 -> 1024                            */
+    float lr;         /* 0 -> 1e-3 (Adam b1 0.9, b2 0.999, eps 1e-8)          */
+    uint64_t seed;    /* shuffling of the rows in every epoch                 */
+} spmm_train_opts;
+
+/*
+ * Train the cost model on the current device: minibatch Adam on the masked
+ * MSE, rows shuffled every epoch (SplitMix64 Fisher-Yates keyed by seed).
+ *   feat: host float[n * 8]; target: host float[n * V] (log ns per tile);
+ *   mask: host uint8[n * V] or NULL; params: host float[PARAMS], initial
+ *   weights in, trained weights out; loss_trace: host double[epochs] (mean
+ *   minibatch loss per epoch) or NULL.  Synchronous.
+ */
+spmm_status_t spmm_selector_train(const float* feat, const float* target, const uint8_t* mask, int64_t n,
+                                  const spmm_train_opts* opts, float* params, double* loss_trace);
+
+/*
+ * Learned selection: features of every tile (for k and dt), cost-model
+ * inference on the device, then spmm_set_variants with the argmin.
+ *   params: host float[PARAMS].  Synchronous.
+ */
+spmm_status_t spmm_select_learned(spmm_handle_t h, const float* params, int k, spmm_xdtype_t dt);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,17 @@ VARIANT_NAMES = ("coo", "row", "hybrid", "wave")
 # spmm_place_t
 SPMM_PLACE_DEVICE, SPMM_PLACE_PINNED_HOST = 0, 1
 
+SPMM_MAX_BUCKETS = 128
+# cost-model parameter layout (one float array; weights row-major [in][out])
+SPMM_MLP_HIDDEN = 64
+SPMM_MLP_OFF_W1 = 0
+SPMM_MLP_OFF_B1 = SPMM_MLP_OFF_W1 + SPMM_NUM_FEATURES * SPMM_MLP_HIDDEN
+SPMM_MLP_OFF_W2 = SPMM_MLP_OFF_B1 + SPMM_MLP_HIDDEN
+SPMM_MLP_OFF_B2 = SPMM_MLP_OFF_W2 + SPMM_MLP_HIDDEN * SPMM_MLP_HIDDEN
+SPMM_MLP_OFF_W3 = SPMM_MLP_OFF_B2 + SPMM_MLP_HIDDEN
+SPMM_MLP_OFF_B3 = SPMM_MLP_OFF_W3 + SPMM_MLP_HIDDEN * SPMM_NUM_VARIANTS
+SPMM_MLP_PARAMS = SPMM_MLP_OFF_B3 + SPMM_NUM_VARIANTS
+
 _STATUS_NAMES = {0: "SPMM_OK", -1: "SPMM_EINVAL", -2: "SPMM_ENOMEM", -3: "SPMM_EHIP",
                  -4: "SPMM_EUNSUPPORTED", -5: "SPMM_ESTATE"}
 
@@ -55,6 +66,15 @@ class spmm_stats_t(ctypes.Structure):
         "sum_nnc", "n_items", "n_parts", "blob_bytes", "desc_bytes")] + [
         ("variant_tiles", ctypes.c_uint64 * SPMM_NUM_VARIANTS),
         ("variant_nnz", ctypes.c_uint64 * SPMM_NUM_VARIANTS)]
+
+
+class spmm_tune_opts(ctypes.Structure):
+    _fields_ = [("min_tiles", ctypes.c_uint32), ("reps", ctypes.c_uint32)]
+
+
+class spmm_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -100,6 +120,23 @@ def load_library():
     L.spmm_decode_tiles.argtypes = [vp, vp, vp, vp]
     L.spmm_model_tiles.restype = i32
     L.spmm_model_tiles.argtypes = [i64, i64, vp, vp, i64, u64p, u64p, u64p]
+    u32, f32 = ctypes.c_uint32, ctypes.c_float
+    for name, args in [
+            ("spmm_tile_features", [vp, i32, i32, vp]),
+            ("spmm_get_variants", [vp, vp]),
+            ("spmm_set_variants", [vp, vp]),
+            ("spmm_selector_collect", [vp, i32, i32, ctypes.POINTER(spmm_tune_opts), vp, vp, vp, vp]),
+            ("spmm_autotune", [vp, i32, i32, ctypes.POINTER(spmm_tune_opts), vp, vp, vp]),
+            ("spmm_mlp_init", [ctypes.c_uint64, vp]),
+            ("spmm_mlp_predict", [vp, vp, i64, vp, vp, vp]),
+            ("spmm_mlp_grad", [vp, vp, vp, vp, i64, vp, vp, vp]),
+            ("spmm_mlp_adam", [vp, vp, vp, vp, i64, f32, f32, f32, f32, vp]),
+            ("spmm_selector_train", [vp, vp, vp, i64, ctypes.POINTER(spmm_train_opts), vp, vp]),
+            ("spmm_select_learned", [vp, vp, i32, i32])]:
+        fn = getattr(L, name)
+        fn.restype = i32
+        fn.argtypes = args
+    del u32
     _lib = L
     return L
 
@@ -301,3 +338,103 @@ def spmm_model_tiles(row_ptr, col_idx, t: int, n_cols: int | None = None):
                                          ctypes.byref(T), ctypes.byref(R), ctypes.byref(C))
     _check(st, "spmm_model_tiles")
     return T.value, R.value, C.value
+
+
+# ------------------------------------------------------------- selection
+
+def spmm_tile_features(h: Handle, k: int, dtype: int = SPMM_X_F32) -> np.ndarray:
+    """Features of every tile, float32 [n_tiles, 8]."""
+    T = spmm_get_stats(h)["n_tiles"]
+    f = np.empty((max(T, 1), SPMM_NUM_FEATURES), dtype=np.float32)
+    _check(load_library().spmm_tile_features(h.ptr, int(k), int(dtype), f.ctypes.data), "spmm_tile_features")
+    return f[:T]
+
+
+def spmm_get_variants(h: Handle) -> np.ndarray:
+    T = spmm_get_stats(h)["n_tiles"]
+    v = np.empty(max(T, 1), dtype=np.uint8)
+    _check(load_library().spmm_get_variants(h.ptr, v.ctypes.data), "spmm_get_variants")
+    return v[:T]
+
+
+def spmm_set_variants(h: Handle, variants) -> None:
+    v = _host(variants, np.uint8)
+    T = spmm_get_stats(h)["n_tiles"]
+    if v.shape != (T,):
+        raise ValueError(f"need one variant per tile ({T})")
+    _check(load_library().spmm_set_variants(h.ptr, v.ctypes.data if T else None), "spmm_set_variants")
+
+
+def spmm_selector_collect(h: Handle, k: int, dtype: int = SPMM_X_F32, min_tiles: int = 0, reps: int = 0,
+                          stream=None):
+    """(bucket of every tile uint32[T], ns per tile float32[n_buckets, V])."""
+    T = spmm_get_stats(h)["n_tiles"]
+    b = np.empty(max(T, 1), dtype=np.uint32)
+    nb = ctypes.c_uint32()
+    ns = np.zeros((SPMM_MAX_BUCKETS, SPMM_NUM_VARIANTS), dtype=np.float32)
+    o = spmm_tune_opts(int(min_tiles), int(reps))
+    st = load_library().spmm_selector_collect(h.ptr, int(k), int(dtype), ctypes.byref(o), b.ctypes.data,
+                                              ctypes.addressof(nb), ns.ctypes.data, _stream(stream))
+    _check(st, "spmm_selector_collect")
+    return b[:T], ns[:nb.value]
+
+
+def spmm_autotune(h: Handle, k: int, dtype: int = SPMM_X_F32, min_tiles: int = 0, reps: int = 0, stream=None):
+    """Exhaustive per-bucket autotune; returns the timing table [n_buckets, V]."""
+    nb = ctypes.c_uint32()
+    ns = np.zeros((SPMM_MAX_BUCKETS, SPMM_NUM_VARIANTS), dtype=np.float32)
+    o = spmm_tune_opts(int(min_tiles), int(reps))
+    st = load_library().spmm_autotune(h.ptr, int(k), int(dtype), ctypes.byref(o), ctypes.addressof(nb),
+                                      ns.ctypes.data, _stream(stream))
+    _check(st, "spmm_autotune")
+    return ns[:nb.value]
+
+
+def spmm_mlp_init(seed: int) -> np.ndarray:
+    p = np.empty(SPMM_MLP_PARAMS, dtype=np.float32)
+    _check(load_library().spmm_mlp_init(ctypes.c_uint64(int(seed) & (2**64 - 1)), p.ctypes.data), "spmm_mlp_init")
+    return p
+
+
+def spmm_mlp_predict(params, feat, out=None, choice=None, n: int | None = None, stream=None):
+    """Device inference: predicted log time per variant and/or the argmin."""
+    n = int(feat.shape[0]) if n is None else int(n)
+    st = load_library().spmm_mlp_predict(_ptr(params), _ptr(feat), n, _ptr(out), _ptr(choice),
+                                         _stream(stream, feat))
+    _check(st, "spmm_mlp_predict")
+
+
+def spmm_mlp_grad(params, feat, target, mask, grad, loss=None, n: int | None = None, stream=None):
+    """Device masked-MSE gradient (and loss) of the cost model."""
+    n = int(feat.shape[0]) if n is None else int(n)
+    st = load_library().spmm_mlp_grad(_ptr(params), _ptr(feat), _ptr(target), _ptr(mask), n, _ptr(grad),
+                                      _ptr(loss), _stream(stream, feat))
+    _check(st, "spmm_mlp_grad")
+
+
+def spmm_mlp_adam(params, m, v, grad, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, stream=None):
+    st = load_library().spmm_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(t), float(lr),
+                                      float(beta1), float(beta2), float(eps), _stream(stream, params))
+    _check(st, "spmm_mlp_adam")
+
+
+def spmm_selector_train(feat, target, mask=None, params=None, *, epochs: int = 0, batch: int = 0,
+                        lr: float = 0.0, seed: int = 0):
+    """Train the cost model on the GPU; returns (params, mean loss per epoch)."""
+    f = _host(feat, np.float32)
+    y = _host(target, np.float32)
+    m = _host(mask, np.uint8)
+    p = spmm_mlp_init(seed) if params is None else np.array(params, dtype=np.float32, copy=True)
+    o = spmm_train_opts(int(epochs), int(batch), float(lr), int(seed) & (2**64 - 1))
+    ne = o.epochs or 30
+    trace = np.zeros(ne, dtype=np.float64)
+    st = load_library().spmm_selector_train(f.ctypes.data, y.ctypes.data, None if m is None else m.ctypes.data,
+                                            int(f.shape[0]), ctypes.byref(o), p.ctypes.data, trace.ctypes.data)
+    _check(st, "spmm_selector_train")
+    return p, trace
+
+
+def spmm_select_learned(h: Handle, params, k: int, dtype: int = SPMM_X_F32) -> None:
+    p = _host(params, np.float32)
+    _check(load_library().spmm_select_learned(h.ptr, p.ctypes.data, int(k), int(dtype)), "spmm_select_learned")

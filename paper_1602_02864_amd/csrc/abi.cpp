@@ -7,13 +7,9 @@
 #include <new>
 #include <string>
 
-#include "spmm_internal.h"
+#include "abi_internal.h"
 
-struct spmm_handle_s {
-    spmm::Handle H;
-};
-
-namespace {
+namespace spmm_abi {
 
 thread_local std::string g_err;
 
@@ -219,22 +215,35 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
     return SPMM_OK;
 }
 
-// Scoped device buffers for the application drivers.
-struct DevBufs {
-    std::vector<void*> p;
-    ~DevBufs() {
-        for (void* q : p) hipFree(q);
-    }
-    template <typename T>
-    T* get(size_t count) {
-        void* q = nullptr;
-        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
-        p.push_back(q);
-        return static_cast<T*>(q);
-    }
-};
+// The SpMM launches alone, with fixed-point exponents already in fexp and X
+// in the handle's column order (used to time buckets of tiles).
+spmm_status_t launch_items_only(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt,
+                                const float* col_scale, float* Y, int64_t ldy, hipStream_t s,
+                                const int32_t* fexp) {
+    spmm::RunArgs a{};
+    a.X = X;
+    a.k = k;
+    a.ldx = ldx;
+    a.dtype = dt;
+    a.col_scale = col_scale;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.stream = s;
+    a.fexp = fexp;
+    a.blob = static_cast<const uint8_t*>(H.d_blob);
+    a.blob_bias = 0;
+    a.items = H.d_items;
+    a.n_items = (uint32_t)H.enc.items.size();
+    a.combine = H.d_combine;
+    a.n_combine = (uint32_t)H.enc.combine.size();
+    a.count = H.d_count;
+    hipError_t e = spmm::launch_spmm(H, a);
+    return e == hipSuccess ? SPMM_OK : hip_fail(e, "kernel launch");
+}
 
-}  // namespace
+}  // namespace spmm_abi
+
+using namespace spmm_abi;
 
 extern "C" {
 

@@ -154,13 +154,11 @@ struct Handle {
     bool uploaded = false;
 };
 
-// Widest column chunk whose per-wavefront accumulator (h x kc int64) fits
-// in 64 KB of LDS, bounded by the handle's max_kc.
 // Strip-table entries of an item's COO stream staged in LDS per wavefront.
 constexpr uint32_t kJTab = 256;
 
-// Columns per launch: a wavefront's 64-bit accumulators for h rows plus its
-// strip table fit in 64 KiB of LDS.
+// Widest column chunk per launch: a wavefront's 64-bit accumulators for h
+// rows plus its strip table fit in 64 KiB of LDS, within the handle's max_kc.
 inline int kc_cap(const Handle& H) {
     int cap = H.max_kc;
     while (cap > 1 && (uint64_t)H.h * cap * 8u + kJTab * 4u > 65536u) cap >>= 1;
@@ -216,6 +214,20 @@ hipError_t launch_pr_update(float* pr, const float* y, int64_t n, double damping
 int gram_blocks();
 hipError_t launch_gram(const float* M, int64_t n, int r, double* part, float* G, hipStream_t s);
 hipError_t launch_mu_update(float* M, const float* S, const float* G, int64_t n, int r, float eps, hipStream_t s);
+
+// mlp_kernels.hip: device workspace of a gradient evaluation over n rows
+struct MlpScratch {
+    float *x, *a1, *a2, *d1, *d2, *d3;  // n x 8, n x 64 (four), n x V
+    double* loss_rows;                   // n
+    uint32_t* count;                     // 1: measured targets
+};
+hipError_t launch_mlp_predict(const float* params, const float* feat, int64_t n, float* out, uint8_t* choice,
+                              hipStream_t s);
+hipError_t launch_mlp_grad(const float* params, const float* feat, const float* target, const uint8_t* mask,
+                           const int32_t* idx, int64_t n, const MlpScratch& w, float* grad, double* loss,
+                           hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int np, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
 
 // quant_kernels.hip
 hipError_t launch_quantize(const float* X, int64_t n, int k, int64_t ldx, int dtype, void* Xq,

@@ -1,0 +1,185 @@
+"""GPU checks of variant selection and of the cost-model kernels.
+
+* MLP inference, masked-MSE gradient and Adam on the device against the
+  FP64 CPU references (gradients within 1e-4 relative per tensor).
+* Training: the loss falls and two runs with one seed give identical weights.
+* Any per-tile variant assignment -- random, autotuned, learned -- computes
+  the same Y: bit-exact against the oracle for integer X.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1602_02864_amd as pk
+import synth
+
+from gpu_util import dev, run_spmm
+
+pytestmark = pytest.mark.gpu
+
+F, H, V = pk.SPMM_NUM_FEATURES, pk.SPMM_MLP_HIDDEN, pk.SPMM_NUM_VARIANTS
+SLICES = {"W1": (pk.SPMM_MLP_OFF_W1, (F, H)), "b1": (pk.SPMM_MLP_OFF_B1, (H,)),
+          "W2": (pk.SPMM_MLP_OFF_W2, (H, H)), "b2": (pk.SPMM_MLP_OFF_B2, (H,)),
+          "W3": (pk.SPMM_MLP_OFF_W3, (H, V)), "b3": (pk.SPMM_MLP_OFF_B3, (V,))}
+
+
+def unflat(p):
+    return {k: np.asarray(p[o:o + int(np.prod(s))], np.float64).reshape(s) for k, (o, s) in SLICES.items()}
+
+
+def flat(d):
+    out = np.zeros(pk.SPMM_MLP_PARAMS)
+    for k, (o, s) in SLICES.items():
+        out[o:o + int(np.prod(s))] = np.asarray(d[k]).ravel()
+    return out
+
+
+def features(n, seed):
+    """Feature rows in the ranges real tiles produce."""
+    u = synth.uniform(n, F, seed=seed).astype(np.float64)
+    scale = np.array([16, 12, 14, 12, 1, 5, 6, 2], np.float64)
+    f = u * scale
+    f[:, 6] = np.floor(f[:, 6])
+    f[:, 7] = np.floor(f[:, 7] * 1.5)
+    return f.astype(np.float32)
+
+
+def t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+@pytest.mark.parametrize("n", [1, 63, 200])
+def test_predict_matches_reference(n):
+    import torch
+    p = pk.spmm_mlp_init(3)
+    f = features(n, 21)
+    out = torch.empty((n, V), device=dev())
+    ch = torch.empty(n, dtype=torch.uint8, device=dev())
+    pk.spmm_mlp_predict(t(p), t(f), out, ch)
+    torch.cuda.synchronize()
+    ref, _ = oracle.mlp_forward(unflat(p), f)
+    got = out.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 1e-4 * (1 + np.abs(ref)))
+    c = ch.cpu().numpy().astype(np.int64)
+    assert c.max() < V
+    # the choice is a minimiser of the reference outputs (up to FP32 ties)
+    chosen = ref[np.arange(n), c]
+    assert np.all(chosen <= ref.min(axis=1) + 1e-4 * (1 + np.abs(ref.min(axis=1))))
+
+
+@pytest.mark.parametrize("n,masked", [(1, False), (300, True), (1024, True)])
+def test_gradient_matches_reference(n, masked):
+    import torch
+    p = pk.spmm_mlp_init(5)
+    # move the biases off zero so that every ReLU pattern is exercised
+    p[pk.SPMM_MLP_OFF_B1:pk.SPMM_MLP_OFF_W2] = synth.uniform(H, 1, seed=31)[:, 0] - 0.5
+    f = features(n, 22)
+    y = (synth.uniform(n, V, seed=23) * 8).astype(np.float32)
+    m = (synth.int07(n, V, seed=24) >= 2).astype(np.uint8) if masked else None
+    grad = torch.empty(pk.SPMM_MLP_PARAMS, device=dev())
+    loss = torch.empty(1, dtype=torch.float64, device=dev())
+    pk.spmm_mlp_grad(t(p), t(f), t(y), None if m is None else t(m), grad, loss)
+    torch.cuda.synchronize()
+    P = unflat(p)
+    mk = np.ones((n, V)) if m is None else m.astype(np.float64)
+    out, cache = oracle.mlp_forward(P, f)
+    ref = oracle.mlp_backward(P, cache, out, y, mk)
+    g = unflat(grad.cpu().numpy())
+    for k in SLICES:
+        den = np.linalg.norm(ref[k])
+        assert np.linalg.norm(g[k] - ref[k]) <= 1e-4 * max(den, 1e-12), k
+    lref = oracle.mse_masked(out, y, mk)
+    assert abs(loss.item() - lref) <= 1e-5 * lref
+
+
+def test_adam_matches_reference():
+    import torch
+    p0 = pk.spmm_mlp_init(8)
+    g = (synth.uniform(pk.SPMM_MLP_PARAMS, 1, seed=41)[:, 0] - 0.5).astype(np.float32)
+    dp, dm, dv = t(p0.copy()), torch.zeros(pk.SPMM_MLP_PARAMS, device=dev()), torch.zeros(pk.SPMM_MLP_PARAMS, device=dev())
+    P, state = unflat(p0), {}
+    for step in range(1, 4):
+        gs = g * np.float32(step)   # a different gradient every step
+        pk.spmm_mlp_adam(dp, dm, dv, t(gs), step, lr=1e-2)
+        P = oracle.adam_step(P, unflat(gs), state, lr=1e-2)
+    torch.cuda.synchronize()
+    got, ref = dp.cpu().numpy().astype(np.float64), flat(P)
+    assert np.all(np.abs(got - ref) <= 1e-6 + 1e-5 * np.abs(ref))
+
+
+def test_training_reduces_loss_and_is_deterministic():
+    n = 3000
+    f = features(n, 51)
+    # a smooth cost surface: per variant a different linear trend in size
+    # and skew plus a kink, the kind of structure the selector must learn
+    a = np.array([[0.9, 0.1], [0.7, 0.5], [0.8, 0.2], [0.6, 0.9]])
+    y = np.stack([a[v, 0] * f[:, 0] + a[v, 1] * f[:, 5] + 0.3 * np.maximum(f[:, 0] - 8, 0) * v
+                  for v in range(V)], axis=1).astype(np.float32)
+    p1, tr1 = pk.spmm_selector_train(f, y, epochs=15, batch=256, lr=3e-3, seed=7)
+    p2, tr2 = pk.spmm_selector_train(f, y, epochs=15, batch=256, lr=3e-3, seed=7)
+    assert np.array_equal(p1, p2) and np.array_equal(tr1, tr2)
+    assert np.all(np.isfinite(tr1)) and tr1[-1] < 0.1 * tr1[0]
+    out, _ = oracle.mlp_forward(unflat(p1), f)
+    assert oracle.mse_masked(out, y, np.ones_like(y)) < 0.1 * float(np.var(y))
+
+
+@pytest.fixture(scope="module")
+def small_graph():
+    rp, col = synth.rmat_csr(13, 16, seed=synth.SEED_GRAPH)
+    return rp, col, rp.shape[0] - 1
+
+
+def _check_exact(hd, rp, col, n, ks=(1, 4, 17)):
+    for k in ks:
+        X = synth.int07(n, k, seed=2)
+        Y = run_spmm(hd, X)
+        ref = oracle.spmm(rp, col, None, X.astype(np.float64))
+        assert np.array_equal(Y, ref.astype(np.float32)), k
+
+
+def test_random_variants_exact(small_graph):
+    rp, col, n = small_graph
+    hd = pk.spmm_build_tiles(rp, col, tile_rows=64, tile_cols=1024)
+    T = pk.spmm_get_stats(hd)["n_tiles"]
+    _check_exact(hd, rp, col, n, ks=(4,))
+    v = (synth.int07(T, 1, seed=19)[:, 0].astype(np.int64) % V).astype(np.uint8)
+    pk.spmm_set_variants(hd, v)   # re-encodes after an upload
+    _check_exact(hd, rp, col, n)
+    hd.close()
+
+
+def test_collect_and_autotune(small_graph):
+    rp, col, n = small_graph
+    hd = pk.spmm_build_tiles(rp, col, tile_rows=64, tile_cols=1024)
+    T = pk.spmm_get_stats(hd)["n_tiles"]
+    b, ns = pk.spmm_selector_collect(hd, 4, min_tiles=32, reps=3)
+    nb = ns.shape[0]
+    assert 1 <= nb <= pk.SPMM_MAX_BUCKETS and b.shape == (T,) and b.max() == nb - 1
+    assert np.all(np.bincount(b, minlength=nb) >= min(32, T))
+    assert np.all(np.isfinite(ns)) and np.all(ns > 0)
+    assert np.all(pk.spmm_get_variants(hd) == pk.SPMM_VAR_HYBRID)   # collect leaves the handle alone
+    table = pk.spmm_autotune(hd, 4, min_tiles=32, reps=3)
+    assert table.shape[0] == nb
+    v = pk.spmm_get_variants(hd)
+    # every tile carries the fastest variant of its bucket in the table
+    b2, _ = pk.spmm_selector_collect(hd, 4, min_tiles=32, reps=1)
+    assert np.array_equal(b, b2)
+    assert np.array_equal(v, np.argmin(table, axis=1)[b].astype(np.uint8))
+    _check_exact(hd, rp, col, n)
+    hd.close()
+
+
+def test_learned_selection_follows_model(small_graph):
+    rp, col, n = small_graph
+    hd = pk.spmm_build_tiles(rp, col, tile_rows=64, tile_cols=1024)
+    p = pk.spmm_mlp_init(13)
+    p[pk.SPMM_MLP_OFF_B3:] = [0.0, 0.3, -0.2, 0.1]
+    pk.spmm_select_learned(hd, p, 4)
+    v = pk.spmm_get_variants(hd).astype(np.int64)
+    f = pk.spmm_tile_features(hd, 4)
+    ref, _ = oracle.mlp_forward(unflat(p), f)
+    chosen = ref[np.arange(v.size), v]
+    assert np.all(chosen <= ref.min(axis=1) + 1e-4 * (1 + np.abs(ref.min(axis=1))))
+    _check_exact(hd, rp, col, n)
+    hd.close()
