@@ -2,21 +2,30 @@
 """SpMM benchmark on one MI355X.
 
 Workload: directed R-MAT graph, scale 25 (33,554,432 vertices), edge factor 44
-(1.476e9 samples, ~1.4e9 stored non-zeros after removing duplicates and
+(1.476e9 samples, ~1.43e9 stored non-zeros after removing duplicates and
 self-loops), a/b/c/d = .57/.19/.19/.05, binary A; X is FP32 uniform[0,1)
 (seed 2) with k in {1, 2, 4, 8, 16, 32}.  One step = one SpMM Y = A X for
 every k of the sweep; the reported value is the aggregate GFLOP/s of a step,
 2 * nnz * sum(k) / step time, with X, Y and the tiles resident in HBM.
 
+Tile variants: "learned" (default) lets the trained cost model pick each
+tile's variant for each k (one resident handle per distinct assignment, all
+built before the timed region); "plain" keeps the build default for every
+tile.  The plain step is timed as well and reported beside the learned one.
+--compare adds every fixed variant and the exhaustive autotuner (per k).
+
 Printed (one JSON line on stdout): the metric, the roofline of the dominant
 kernel under the paper-tile byte model (16K x 16K tiles: A as SCSR, each
 tile reading the X rows of its non-empty columns once, each Y row written
-once), and the CPU oracle timed on a bounded sample of rows, whose results
-also give a sampled full-size parity check of the GPU output.
+once), the HBM traffic of that kernel from committed counter runs when they
+were taken on the current kernel source, and the CPU oracle timed on a
+bounded sample of rows, whose results also give a sampled full-size parity
+check of the GPU output.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+KERNEL_SRC = os.path.join(ROOT, "paper_1602_02864_amd", "csrc", "spmm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmm_items_rmat-s25-ef44.txt")
 
 
 def log(msg: str) -> None:
@@ -41,6 +52,66 @@ def model_bytes(T: int, R: int, C: int, nnz: int, n: int, k: int, xbytes: int = 
             "floor": b_a + n * k * xbytes + b_y}
 
 
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kc: int):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on this kernel source and column chunk."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            a, b = line.split("=", 1)
+            vals[a.strip()] = b.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or vals.get("kc") != str(kc):
+        return None
+    try:
+        return int(float(vals["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def time_step(runs, steps, warmup, stream):
+    """runs: list of (k, callable).  Returns (ms per step, {k: ms per SpMM})."""
+    import numpy as np
+    import torch
+    for _ in range(max(warmup, 1)):
+        for _, fn in runs:
+            fn()
+    torch.cuda.synchronize()
+    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)] for k, _ in runs}
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for s in range(steps):
+        for k, fn in runs:
+            a, b = ev[k][s]
+            a.record(stream)
+            fn()
+            b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_k = {k: float(np.mean([a.elapsed_time(b) for a, b in ev[k]])) for k, _ in runs}
+    return wall * 1e3 / steps, ms_k
+
+
+def time_one(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,7 +120,10 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=25)
     ap.add_argument("--edge-factor", type=float, default=44.0)
     ap.add_argument("--ks", default="1,2,4,8,16,32")
-    ap.add_argument("--variant", type=int, default=-1, help="fixed tile variant (-1 = default)")
+    ap.add_argument("--select", choices=["learned", "plain"], default="learned")
+    ap.add_argument("--weights", default=None, help="cost-model weights (.npy)")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time every fixed variant and the exhaustive autotuner per k")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--tile-cols", type=int, default=0)
     ap.add_argument("--item-nnz", type=int, default=0)
@@ -69,10 +143,17 @@ def main() -> int:
 
     import paper_1602_02864_amd as pk
     import synth
+    from paper_1602_02864_amd.selector_train import WEIGHTS
 
     ks = [int(x) for x in args.ks.split(",")]
     dev = torch.device("cuda:0")
     torch.cuda.init()
+    params = None
+    if args.select == "learned" or args.compare:
+        wpath = args.weights or WEIGHTS
+        if not os.path.exists(wpath):
+            raise SystemExit(f"{wpath} is missing: train it with python -m paper_1602_02864_amd.selector_train")
+        params = np.load(wpath, allow_pickle=False).astype(np.float32)
 
     t0 = time.perf_counter()
     rp, col = synth.rmat_csr(args.scale, args.edge_factor, seed=synth.SEED_GRAPH)
@@ -86,55 +167,90 @@ def main() -> int:
     t_model = time.perf_counter() - t0
     log(f"byte model (16K tiles): tiles={T} sum_nnr={R} sum_nnc={C} ({t_model:.1f}s)")
 
+    def build():
+        return pk.spmm_build_tiles(rp, col, tile_rows=args.tile_rows, tile_cols=args.tile_cols,
+                                   item_nnz=args.item_nnz, max_kc=args.max_kc, validate=False)
+
     t0 = time.perf_counter()
-    h = pk.spmm_build_tiles(rp, col, tile_rows=args.tile_rows, tile_cols=args.tile_cols,
-                            fixed_variant=args.variant, item_nnz=args.item_nnz,
-                            max_kc=args.max_kc, validate=False)
+    h_plain = build()
     t_build = time.perf_counter() - t0
-    st = pk.spmm_get_stats(h)
-    log(f"tiles built in {t_build:.1f}s: items={st['n_items']} parts={st['n_parts']} "
-        f"blob={st['blob_bytes'] / nnz:.2f} B/nnz")
+    st = pk.spmm_get_stats(h_plain)
+    max_kc = args.max_kc or 16
+    log(f"tiles built in {t_build:.1f}s: tiles={st['n_tiles']} items={st['n_items']} "
+        f"parts={st['n_parts']} blob={st['blob_bytes'] / nnz:.2f} B/nnz")
+
+    # learned selection: one handle per distinct per-tile assignment
+    handle_of = {k: h_plain for k in ks}
+    select_info = {"mode": args.select}
+    handles = [h_plain]
+    t_select = 0.0
+    if args.select == "learned":
+        t0 = time.perf_counter()
+        pd = torch.from_numpy(params).to(dev)
+        assign = {}
+        for k in ks:
+            f = torch.from_numpy(pk.spmm_tile_features(h_plain, k)).to(dev)
+            ch = torch.empty(f.shape[0], dtype=torch.uint8, device=dev)
+            pk.spmm_mlp_predict(pd, f, None, ch)
+            torch.cuda.synchronize()
+            assign[k] = ch.cpu().numpy()
+        groups = []
+        for k in ks:
+            for g in groups:
+                if np.array_equal(assign[g[0]], assign[k]):
+                    g.append(k)
+                    break
+            else:
+                groups.append([k])
+        plain_v = pk.spmm_get_variants(h_plain)
+        for g in groups:
+            v = assign[g[0]]
+            if np.array_equal(v, plain_v):
+                hg = h_plain
+            else:
+                hg = build()
+                pk.spmm_set_variants(hg, v)
+                handles.append(hg)
+            for k in g:
+                handle_of[k] = hg
+        t_select = time.perf_counter() - t0
+        select_info.update({
+            "handles": len(handles), "groups": groups, "select_s": round(t_select, 1),
+            "tiles_per_variant": {str(k): np.bincount(assign[k], minlength=pk.SPMM_NUM_VARIANTS).tolist()
+                                  for k in ks}})
+        log(f"learned selection in {t_select:.1f}s: groups {groups}")
 
     Xs, Ys = {}, {}
     for k in ks:
         Xs[k] = torch.from_numpy(synth.uniform(n, k, seed=synth.SEED_X)).to(dev)
         Ys[k] = torch.empty((n, k), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
-    log("X/Y resident; first call uploads the tiles")
+    log("X/Y resident; first calls upload the tiles")
 
     stream = torch.cuda.current_stream(dev)
-    for _ in range(max(args.warmup, 1)):
-        for k in ks:
-            pk.spmm_run(h, Xs[k], Ys[k], stream=stream)
-    torch.cuda.synchronize()
-    log("warmup done")
 
-    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)] for k in ks}
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for s in range(args.steps):
-        for k in ks:
-            a, b = ev[k][s]
-            a.record(stream)
-            pk.spmm_run(h, Xs[k], Ys[k], stream=stream)
-            b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_k = {k: float(np.mean([a.elapsed_time(b) for a, b in ev[k]])) for k in ks}
-    log("timed: " + ", ".join(f"k={k}: {ms_k[k]:.3f} ms" for k in ks))
+    def runs_for(hmap):
+        return [(k, (lambda k=k: pk.spmm_run(hmap[k], Xs[k], Ys[k], stream=stream))) for k in ks]
+
+    plain_ms_step, plain_ms_k = time_step(runs_for({k: h_plain for k in ks}), args.steps, args.warmup, stream)
+    log("plain: " + ", ".join(f"k={k}: {plain_ms_k[k]:.3f} ms" for k in ks))
+    if args.select == "learned":
+        ms_step, ms_k = time_step(runs_for(handle_of), args.steps, args.warmup, stream)
+        log("learned: " + ", ".join(f"k={k}: {ms_k[k]:.3f} ms" for k in ks))
+    else:
+        ms_step, ms_k = plain_ms_step, plain_ms_k
 
     flop_step = sum(2.0 * nnz * k for k in ks)
-    ms_step = wall * 1e3 / args.steps
     value = flop_step / (ms_step * 1e-3) / 1e9
+    plain_value = flop_step / (plain_ms_step * 1e-3) / 1e9
 
-    max_kc = args.max_kc or 32
     per_k = {}
     for k in ks:
         mb = model_bytes(T, R, C, nnz, n, k)
-        launches = -(-k // max_kc) if k > max_kc else 1
+        launches = -(-k // max_kc)
         per_k[str(k)] = {
             "ms": round(ms_k[k], 4),
+            "plain_ms": round(plain_ms_k[k], 4),
             "gflops": round(2.0 * nnz * k / (ms_k[k] * 1e-3) / 1e9, 2),
             "model_gb": round(mb["total"] / 1e9, 4),
             "model_frac": round(mb["total"] / (ms_k[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -145,14 +261,47 @@ def main() -> int:
     mb = model_bytes(T, R, C, nnz, n, kdom)
     launches = per_k[str(kdom)]["launches"]
     # per launch: the whole A, this launch's share of the X columns and of Y
-    kc = kdom // launches
+    kc = -(-kdom // launches)
     launch_bytes = mb["A"] + C * kc * 4 + n * kc * 4
     launch_ms = ms_k[kdom] / launches
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kc),
                 "kernel": f"spmm_items k={kdom} (kc={kc}, {launches} launch(es) per SpMM)",
-                "bytes_per_launch": int(launch_bytes), "ms_per_launch": round(launch_ms, 4)}
+                "bytes_per_launch": int(launch_bytes), "ms_per_launch": round(launch_ms, 4),
+                "kernel_source_sha256_16": kernel_source_hash()}
+
+    compare = None
+    if args.compare:
+        compare = {"plain": {str(k): round(plain_ms_k[k], 4) for k in ks}}
+        hc = h_plain
+        for v, name in enumerate(pk.VARIANT_NAMES):
+            pk.spmm_set_variants(hc, np.full(st["n_tiles"], v, np.uint8))
+            compare[f"fixed_{name}"] = {str(k): round(time_one(
+                lambda k=k: pk.spmm_run(hc, Xs[k], Ys[k], stream=stream)), 4) for k in ks}
+            log(f"fixed {name}: {compare[f'fixed_{name}']}")
+        compare["autotune"], compare["autotune_s"] = {}, {}
+        for k in ks:
+            t0 = time.perf_counter()
+            pk.spmm_autotune(hc, k)
+            compare["autotune_s"][str(k)] = round(time.perf_counter() - t0, 1)
+            compare["autotune"][str(k)] = round(time_one(lambda: pk.spmm_run(hc, Xs[k], Ys[k], stream=stream)), 4)
+            log(f"autotune k={k}: {compare['autotune'][str(k)]} ms ({compare['autotune_s'][str(k)]}s)")
+        compare["learned"] = {}
+        for k in ks:
+            pk.spmm_select_learned(hc, params, k)
+            compare["learned"][str(k)] = round(time_one(lambda: pk.spmm_run(hc, Xs[k], Ys[k], stream=stream)), 4)
+        log(f"learned (same protocol): {compare['learned']}")
+        tot = {m: sum(d.values()) for m, d in compare.items() if not m.endswith("_s")}
+        compare["sweep_gflops"] = {m: round(flop_step / (t * 1e-3) / 1e9, 1) for m, t in tot.items()}
+        best_fixed = min(t for m, t in tot.items() if m.startswith("fixed_"))
+        compare["learned_over_autotune"] = round(tot["learned"] / tot["autotune"], 4)
+        compare["learned_over_best_fixed"] = round(tot["learned"] / best_fixed, 4)
+        # re-select for the parity check below (Y of the last comparison run)
+        for k in ks:
+            pk.spmm_run(handle_of[k], Xs[k], Ys[k], stream=stream)
+        torch.cuda.synchronize()
 
     cpu = None
     parity = None
@@ -195,7 +344,7 @@ def main() -> int:
         log(f"cpu oracle {cpu_gflops:.2f} GFLOP/s over {t_cpu:.1f}s; parity max err {parity['max_rel_frob_err']:.3g}")
 
     out = {
-        "metric": "SpMM GFLOP/s (2*nnz*k/s) over the k sweep, % HBM roofline",
+        "metric": "SpMM GFLOP/s (2*nnz*k/s) over the k sweep, % HBM roofline; learned-tuned vs plain",
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -209,18 +358,24 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"rmat-s{args.scale}-ef{int(args.edge_factor)}-directed-binary",
                    "n": n, "nnz": nnz, "k": ks, "x": "f32 uniform[0,1) seed 2", "graph_seed": 1,
-                   "tile_rows": st["tile_rows"], "tile_cols": st["tile_cols"],
-                   "variant": args.variant, "max_kc": max_kc},
+                   "tile_rows": st["tile_rows"], "tile_cols": st["tile_cols"], "max_kc": max_kc,
+                   "select": args.select},
+        "plain": {"value": round(plain_value, 2), "ms_per_step": round(plain_ms_step, 4),
+                  "learned_over_plain": round(value / plain_value, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
         "per_k": per_k,
+        "selection": select_info,
+        "compare_ms": compare,
         "tiles": {k: st[k] for k in ("n_tiles", "n_items", "n_parts", "blob_bytes", "sum_nnr", "sum_nnc")},
         "model_16k": {"tiles": T, "sum_nnr": R, "sum_nnc": C},
-        "prep_s": {"generate": round(t_gen, 1), "model": round(t_model, 1), "build": round(t_build, 1)},
+        "prep_s": {"generate": round(t_gen, 1), "model": round(t_model, 1), "build": round(t_build, 1),
+                   "select": round(t_select, 1)},
     }
     print(json.dumps(out), flush=True)
-    h.close()
+    for hd in handles:
+        hd.close()
     return 0
 
 

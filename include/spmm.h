@@ -96,7 +96,7 @@ typedef struct {
     uint32_t threads;        /* host threads for the build; 0 -> all cores       */
     uint32_t validate;       /* 1 -> reject unsorted/duplicate/out-of-range CSR  */
     uint32_t max_kc;         /* widest block of X columns one kernel launch
-                                 accumulates: 16 or 32; 0 -> 32                   */
+                                 accumulates: 16 or 32; 0 -> 16                   */
     uint32_t keep_order;     /* 0 (default): tiles index columns by descending
                                  in-degree, and spmm_run first gathers X into that
                                  row order (a handle-owned buffer), so the X rows

@@ -260,7 +260,7 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         if (row_ptr[n_rows] > 0 && !col_idx) return fail(SPMM_EINVAL, "col_idx is NULL");
         spmm_build_opts o{};
         if (opts) o = *opts;
-        if (o.max_kc == 0) o.max_kc = 32;
+        if (o.max_kc == 0) o.max_kc = 16;
         if (o.max_kc != 16 && o.max_kc != 32) return fail(SPMM_EINVAL, "max_kc must be 16 or 32");
         if (o.tile_rows == 0) o.tile_rows = spmm::kDefaultTileRows;
         if (o.tile_cols == 0) o.tile_cols = spmm::kDefaultTileCols;

@@ -1,0 +1,163 @@
+"""Train the per-tile cost model on timings of generated graphs.
+
+    python -m paper_1602_02864_amd.selector_train [--out DIR] [--quick]
+
+Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 20-22 with graph
+seeds 11-16, directed and symmetrised, edge factors 8-44 -- never seed 1,
+the seed of the benchmark graphs.  Each graph is tiled with the library's
+default geometry (64-row tile rows, 65536-column strips).  For every graph,
+column count k and X type, spmm_selector_collect times each variant on
+every bucket of similar tiles; a training row is one tile: its 8 features
+and, per variant, the log of its bucket's nanoseconds per tile.  At most
+``--per-bucket`` tiles of a bucket are kept per collection, so large
+buckets of tiny tiles do not crowd out the rare large tiles that carry most
+of the time.
+
+Training runs on the GPU (spmm_selector_train: minibatch Adam on the MSE).
+A held-out graph (seed 17) measures the result: per (k, type), the time the
+learned choice costs over the per-bucket optimum of the exhaustive timing
+(the regret), next to the regret of each fixed variant.
+
+Writes DIR/selector_weights.npy (float32[SPMM_MLP_PARAMS]) and
+DIR/selector_train.json (data, loss trace, held-out regrets).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import paper_1602_02864_amd as pk  # noqa: E402
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.npy")
+
+# (scale, edge factor, graph seed, symmetrise)
+TRAIN_GRAPHS = [(20, 16, 11, False), (21, 44, 12, False), (22, 8, 13, True),
+                (21, 28, 14, True), (22, 44, 15, False)]
+HELD_OUT = (22, 32, 17, False)
+QUICK_GRAPHS = [(16, 16, 11, False), (17, 8, 13, True)]
+QUICK_HELD_OUT = (17, 16, 17, False)
+# (k, X type) pairs timed per graph
+RUNS = [(1, pk.SPMM_X_F32), (4, pk.SPMM_X_F32), (16, pk.SPMM_X_F32), (32, pk.SPMM_X_F32),
+        (64, pk.SPMM_X_F32), (16, pk.SPMM_X_BF16), (16, pk.SPMM_X_FP8_E4M3)]
+DT_NAMES = {pk.SPMM_X_F32: "f32", pk.SPMM_X_BF16: "bf16", pk.SPMM_X_FP8_E4M3: "fp8"}
+
+
+def log(msg: str) -> None:
+    print(f"[selector {time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def graph(scale, ef, seed, sym):
+    import synth
+    return synth.rmat_csr(scale, ef, seed=seed, symmetrize=sym)
+
+
+def collect_rows(h, k, dt, per_bucket, rng):
+    """Feature rows and log-ns labels of (at most per_bucket) tiles per bucket."""
+    b, ns = pk.spmm_selector_collect(h, k, dt)
+    f = pk.spmm_tile_features(h, k, dt)
+    keep = []
+    for q in range(ns.shape[0]):
+        idx = np.flatnonzero(b == q)
+        if idx.size > per_bucket:
+            idx = rng.choice(idx, per_bucket, replace=False)
+        keep.append(idx)
+    keep = np.concatenate(keep) if keep else np.zeros(0, np.int64)
+    y = np.log(np.maximum(ns[b[keep]], 1e-3)).astype(np.float32)
+    return f[keep], y, b, ns
+
+
+def regrets(h, params, k, dt, keep=None):
+    """Time over the per-bucket optimum: learned choice and each fixed variant."""
+    b, ns = pk.spmm_selector_collect(h, k, dt)
+    f = pk.spmm_tile_features(h, k, dt)
+    if keep is not None:
+        # distinct (features, bucket) rows with their tile counts
+        u, inv, cnt = np.unique(np.concatenate([f, b[:, None].astype(np.float32)], axis=1), axis=0,
+                                return_inverse=True, return_counts=True)
+        keep[f"k{k}_{DT_NAMES[dt]}"] = (u, cnt, ns)
+    import torch
+    dev = torch.device("cuda:0")
+    ch = torch.empty(f.shape[0], dtype=torch.uint8, device=dev)
+    pk.spmm_mlp_predict(torch.from_numpy(params).to(dev), torch.from_numpy(f).to(dev), None, ch)
+    torch.cuda.synchronize()
+    c = ch.cpu().numpy().astype(np.int64)
+    best = ns.min(axis=1)[b].sum()
+    out = {"learned": float(ns[b, c].sum() / best - 1.0)}
+    for v, name in enumerate(pk.VARIANT_NAMES):
+        out[name] = float(ns[b, v].sum() / best - 1.0)
+    return out
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", default=os.path.dirname(WEIGHTS))
+    ap.add_argument("--quick", action="store_true", help="small graphs (a functional run)")
+    ap.add_argument("--per-bucket", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--dump", action="store_true",
+                    help="also write the training rows and held-out timing tables (.npz)")
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.init()
+    rng = np.random.default_rng(args.seed)
+    graphs = QUICK_GRAPHS if args.quick else TRAIN_GRAPHS
+    held = QUICK_HELD_OUT if args.quick else HELD_OUT
+    F, Y, meta = [], [], []
+    for g in graphs:
+        t0 = time.perf_counter()
+        rp, col = graph(*g)
+        h = pk.spmm_build_tiles(rp, col, validate=False)
+        T = pk.spmm_get_stats(h)["n_tiles"]
+        for k, dt in RUNS:
+            f, y, b, ns = collect_rows(h, k, dt, args.per_bucket, rng)
+            F.append(f)
+            Y.append(y)
+            meta.append({"graph": g, "k": k, "x": DT_NAMES[dt], "tiles": T, "buckets": int(ns.shape[0]),
+                         "rows": int(f.shape[0])})
+            log(f"graph {g} k={k} {DT_NAMES[dt]}: {ns.shape[0]} buckets, {f.shape[0]} rows")
+        h.close()
+        log(f"graph {g} done in {time.perf_counter() - t0:.1f}s")
+    F = np.concatenate(F)
+    Y = np.concatenate(Y)
+    log(f"training on {F.shape[0]} rows")
+    t0 = time.perf_counter()
+    params, trace = pk.spmm_selector_train(F, Y, epochs=args.epochs, batch=1024, lr=1e-3, seed=args.seed)
+    t_train = time.perf_counter() - t0
+    log(f"trained in {t_train:.1f}s: loss {trace[0]:.4f} -> {trace[-1]:.4f}")
+    rp, col = graph(*held)
+    h = pk.spmm_build_tiles(rp, col, validate=False)
+    held_res = []
+    held_tables = {} if args.dump else None
+    for k, dt in RUNS:
+        r = regrets(h, params, k, dt, held_tables)
+        held_res.append({"k": k, "x": DT_NAMES[dt], "regret": r})
+        log(f"held-out k={k} {DT_NAMES[dt]}: " + ", ".join(f"{a}={v * 100:.1f}%" for a, v in r.items()))
+    h.close()
+    os.makedirs(args.out, exist_ok=True)
+    np.save(os.path.join(args.out, "selector_weights.npy"), params.astype(np.float32))
+    with open(os.path.join(args.out, "selector_train.json"), "w") as fh:
+        json.dump({"graphs": [list(g) for g in graphs], "held_out": list(held), "runs": meta,
+                   "rows": int(F.shape[0]), "epochs": args.epochs, "seed": args.seed,
+                   "train_s": round(t_train, 2), "loss_trace": [float(x) for x in trace],
+                   "held_out_regret": held_res}, fh, indent=1)
+    if args.dump:
+        np.savez_compressed(os.path.join(args.out, "selector_rows.npz"), feat=F, target=Y)
+        np.savez_compressed(os.path.join(args.out, "selector_heldout.npz"),
+                            **{f"{name}_{part}": arr for name, (u, cnt, ns) in held_tables.items()
+                               for part, arr in (("featbucket", u), ("count", cnt), ("ns", ns))})
+    log(f"wrote {args.out}/selector_weights.npy")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
