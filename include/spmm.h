@@ -86,7 +86,7 @@ typedef enum {
 
 /* Build options.  A zero-initialised struct selects every default. */
 typedef struct {
-    uint32_t tile_rows;      /* h: rows per tile row; 0 -> 64; 1..4096           */
+    uint32_t tile_rows;      /* h: rows per tile row; 0 -> 32; 1..4096           */
     uint32_t tile_cols;      /* w: columns per tile; 0 -> 65536; power of 2,
                                  <= 65536 (16-bit local column index)           */
     int32_t fixed_variant;   /* variant of every tile; < 0 -> SPMM_VAR_HYBRID    */
@@ -96,7 +96,7 @@ typedef struct {
     uint32_t threads;        /* host threads for the build; 0 -> all cores       */
     uint32_t validate;       /* 1 -> reject unsorted/duplicate/out-of-range CSR  */
     uint32_t max_kc;         /* widest block of X columns one kernel launch
-                                 accumulates: 16 or 32; 0 -> 16                   */
+                                 accumulates: 16 or 32; 0 -> 32                   */
     uint32_t keep_order;     /* 0 (default): tiles index columns by descending
                                  in-degree, and spmm_run first gathers X into that
                                  row order (a handle-owned buffer), so the X rows
@@ -244,6 +244,17 @@ spmm_status_t spmm_nmf(spmm_handle_t hA, spmm_handle_t hAT, int rank, int iters,
  * Errors: SPMM_EINVAL (NULL arguments, values for a binary A), SPMM_ENOMEM.
  */
 spmm_status_t spmm_decode_tiles(spmm_handle_t h, int64_t* row_ptr, int32_t* col_idx, float* values);
+
+/*
+ * Kernel timing.  Between spmm_timing_begin and spmm_timing_end, every
+ * spmm_run on h records a HIP event pair on its stream around its SpMM
+ * launches only (not the X reordering or fixed-point exponent kernels),
+ * without host synchronisation.  spmm_timing_end waits for the recorded
+ * events, returns the summed milliseconds and the number of runs, and stops
+ * recording.  Not for use while a stream that runs on h is being captured.
+ */
+spmm_status_t spmm_timing_begin(spmm_handle_t h);
+spmm_status_t spmm_timing_end(spmm_handle_t h, double* total_ms, uint64_t* n_runs);
 
 /* Shape and storage statistics of a handle. */
 typedef struct {

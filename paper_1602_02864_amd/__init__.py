@@ -132,7 +132,9 @@ def load_library():
             ("spmm_mlp_grad", [vp, vp, vp, vp, i64, vp, vp, vp]),
             ("spmm_mlp_adam", [vp, vp, vp, vp, i64, f32, f32, f32, f32, vp]),
             ("spmm_selector_train", [vp, vp, vp, i64, ctypes.POINTER(spmm_train_opts), vp, vp]),
-            ("spmm_select_learned", [vp, vp, i32, i32])]:
+            ("spmm_select_learned", [vp, vp, i32, i32]),
+            ("spmm_timing_begin", [vp]),
+            ("spmm_timing_end", [vp, vp, vp])]:
         fn = getattr(L, name)
         fn.restype = i32
         fn.argtypes = args
@@ -304,6 +306,18 @@ def spmm_nmf(hA: Handle, hAT: Handle, W, H, iters: int = 10, eps: float = 1e-9, 
     st = load_library().spmm_nmf(hA.ptr, hAT.ptr, int(W.shape[1]), int(iters), float(eps), _ptr(W), _ptr(H),
                                  _stream(stream, W))
     _check(st, "spmm_nmf")
+
+
+def spmm_timing_begin(h: Handle) -> None:
+    _check(load_library().spmm_timing_begin(h.ptr), "spmm_timing_begin")
+
+
+def spmm_timing_end(h: Handle):
+    """(summed SpMM-launch milliseconds, runs) since spmm_timing_begin."""
+    ms, runs = ctypes.c_double(), ctypes.c_uint64()
+    _check(load_library().spmm_timing_end(h.ptr, ctypes.addressof(ms), ctypes.addressof(runs)),
+           "spmm_timing_end")
+    return ms.value, runs.value
 
 
 def spmm_get_stats(h: Handle) -> dict:

@@ -45,6 +45,10 @@ void free_device(spmm::Handle& H) {
     for (void* q : H.ring) hipFree(q);
     for (hipEvent_t e : H.ev_ready) hipEventDestroy(e);
     for (hipEvent_t e : H.ev_free) hipEventDestroy(e);
+    for (hipEvent_t e : H.timing_ev) hipEventDestroy(e);
+    H.timing_ev.clear();
+    H.timing_used = 0;
+    H.timing = false;
     H.ring.clear();
     H.ev_ready.clear();
     H.ev_free.clear();
@@ -210,8 +214,22 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
     a.combine = H.d_combine;
     a.n_combine = (uint32_t)H.enc.combine.size();
     a.count = H.d_count;
+    hipEvent_t* ev = nullptr;
+    if (H.timing) {
+        if (H.timing_used + 2 > H.timing_ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t q = nullptr;
+                if (hipEventCreate(&q) != hipSuccess) return fail(SPMM_EHIP, "hipEventCreate");
+                H.timing_ev.push_back(q);
+            }
+        }
+        ev = &H.timing_ev[H.timing_used];
+        H.timing_used += 2;
+        hipEventRecord(ev[0], s);
+    }
     hipError_t e = spmm::launch_spmm(H, a);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (ev) hipEventRecord(ev[1], s);
     return SPMM_OK;
 }
 
@@ -260,7 +278,7 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         if (row_ptr[n_rows] > 0 && !col_idx) return fail(SPMM_EINVAL, "col_idx is NULL");
         spmm_build_opts o{};
         if (opts) o = *opts;
-        if (o.max_kc == 0) o.max_kc = 16;
+        if (o.max_kc == 0) o.max_kc = 32;
         if (o.max_kc != 16 && o.max_kc != 32) return fail(SPMM_EINVAL, "max_kc must be 16 or 32");
         if (o.tile_rows == 0) o.tile_rows = spmm::kDefaultTileRows;
         if (o.tile_cols == 0) o.tile_cols = spmm::kDefaultTileCols;
@@ -440,6 +458,13 @@ spmm_status_t spmm_pagerank(spmm_handle_t h, float damping, int iters, uint32_t 
         hipStreamWaitEvent(cs, ev, 0);
         if (!(flags & SPMM_PR_INIT_GIVEN)) spmm::launch_pr_init(pr, n, (float)(1.0 / (double)n), cs);
         const int redistribute = (flags & SPMM_PR_NO_REDISTRIBUTE) ? 0 : 1;
+        // no timing events inside the captured iterations
+        struct TimingOff {
+            spmm::Handle& H;
+            bool was;
+            ~TimingOff() { H.timing = was; }
+        } timing_off{H, H.timing};
+        H.timing = false;
         const int32_t* perm = H.relabel ? H.d_col_old : nullptr;
         auto enqueue = [&]() -> spmm_status_t {
             for (int it = 0; it < iters; ++it) {
@@ -540,6 +565,32 @@ spmm_status_t spmm_quantize_x(const float* X, int64_t n, int k, int64_t ldx, spm
     hipError_t e = spmm::launch_quantize(X, n, k, ldx, dt, Xq, ldq, col_scale,
                                          (flags & SPMM_QUANT_SCALES_GIVEN) != 0, s);
     return e == hipSuccess ? SPMM_OK : hip_fail(e, "quantize launch");
+}
+
+spmm_status_t spmm_timing_begin(spmm_handle_t h) {
+    if (!h) return fail(SPMM_EINVAL, "handle is NULL");
+    h->H.timing = true;
+    h->H.timing_used = 0;
+    return SPMM_OK;
+}
+
+spmm_status_t spmm_timing_end(spmm_handle_t h, double* total_ms, uint64_t* n_runs) {
+    if (!h || !total_ms) return fail(SPMM_EINVAL, "NULL argument");
+    spmm::Handle& H = h->H;
+    double sum = 0.0;
+    for (size_t i = 0; i + 1 < H.timing_used; i += 2) {
+        hipError_t e = hipEventSynchronize(H.timing_ev[i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "timing");
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, H.timing_ev[i], H.timing_ev[i + 1])) != hipSuccess)
+            return hip_fail(e, "hipEventElapsedTime");
+        sum += ms;
+    }
+    *total_ms = sum;
+    if (n_runs) *n_runs = H.timing_used / 2;
+    H.timing = false;
+    H.timing_used = 0;
+    return SPMM_OK;
 }
 
 spmm_status_t spmm_get_stats(spmm_handle_t h, spmm_stats_t* out) {

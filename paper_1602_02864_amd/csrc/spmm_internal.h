@@ -14,7 +14,7 @@
 namespace spmm {
 
 constexpr uint32_t kMaxTileRows = 4096;
-constexpr uint32_t kDefaultTileRows = 64;
+constexpr uint32_t kDefaultTileRows = 32;
 constexpr uint32_t kDefaultTileCols = 65536;
 constexpr uint32_t kDefaultItemNnz = 16384;
 constexpr uint32_t kMaxItemNnz = 131072;
@@ -152,6 +152,10 @@ struct Handle {
     std::vector<hipEvent_t> ev_ready, ev_free;
     int device = 0;
     bool uploaded = false;
+    // optional timing of the SpMM launches of each run (event pairs)
+    bool timing = false;
+    size_t timing_used = 0;
+    std::vector<hipEvent_t> timing_ev;  // start, stop, start, stop, ...
 };
 
 // Strip-table entries of an item's COO stream staged in LDS per wavefront.

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void spmm_items(
     constexpr bool has_val = HV;        // weighted A
     constexpr int G = KC / VW;          // lanes per X row
     constexpr int P = 64 / G;           // entries per step
-    constexpr int U = KC <= 2 ? 8 : KC <= 4 ? 4 : 2;  // steps in flight per lane
+    constexpr int U = KC <= 2 ? 8 : KC <= 8 ? 4 : 8;  // steps in flight per lane
     extern __shared__ unsigned long long lds[];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;

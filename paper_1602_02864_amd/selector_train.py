@@ -5,7 +5,7 @@
 Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 20-22 with graph
 seeds 11-16, directed and symmetrised, edge factors 8-44 -- never seed 1,
 the seed of the benchmark graphs.  Each graph is tiled with the library's
-default geometry (64-row tile rows, 65536-column strips).  For every graph,
+default geometry (32-row tile rows, 65536-column strips).  For every graph,
 column count k and X type, spmm_selector_collect times each variant on
 every bucket of similar tiles; a training row is one tile: its 8 features
 and, per variant, the log of its bucket's nanoseconds per tile.  At most
