@@ -117,8 +117,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--scale", type=int, default=25)
-    ap.add_argument("--edge-factor", type=float, default=44.0)
+    ap.add_argument("--scale", type=int, default=None,
+                    help="graph scale (25 for spmm/stream, 26 for precision/apps)")
+    ap.add_argument("--edge-factor", type=float, default=None,
+                    help="edge factor (44 for spmm/stream, 28 for precision/apps)")
     ap.add_argument("--ks", default="1,2,4,8,16,32")
     ap.add_argument("--select", choices=["learned", "plain"], default="learned")
     ap.add_argument("--weights", default=None, help="cost-model weights (.npy)")
@@ -133,7 +135,14 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="run a plain device copy of this many GiB first (counter calibration)")
+    ap.add_argument("--mode", default="spmm",
+                    help="spmm (default) | stream | precision | apps | precision,apps")
+    ap.add_argument("--stream-kib", type=int, default=0, help="streamed mode: bytes per transfer group")
+    ap.add_argument("--ring-depth", type=int, default=0, help="streamed mode: device ring slots")
     args = ap.parse_args()
+    modes = args.mode.split(",")
+    if args.gpus == 1 and modes != ["spmm"]:
+        return run_other_modes(args, modes)
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -148,6 +157,8 @@ def main() -> int:
     from paper_1602_02864_amd.selector_train import WEIGHTS
 
     ks = [int(x) for x in args.ks.split(",")]
+    args.scale = 25 if args.scale is None else args.scale
+    args.edge_factor = 44.0 if args.edge_factor is None else args.edge_factor
     dev = torch.device("cuda:0")
     torch.cuda.init()
     if args.copy_gib > 0:
@@ -166,7 +177,7 @@ def main() -> int:
         params = np.load(wpath, allow_pickle=False).astype(np.float32)
 
     t0 = time.perf_counter()
-    rp, col = synth.rmat_csr(args.scale, args.edge_factor, seed=synth.SEED_GRAPH)
+    rp, col = synth.rmat_csr(args.scale, args.edge_factor, seed=synth.SEED_GRAPH, progress=log)
     n = rp.shape[0] - 1
     nnz = int(col.shape[0])
     t_gen = time.perf_counter() - t0
@@ -400,6 +411,199 @@ def main() -> int:
     print(json.dumps(out), flush=True)
     for hd in handles:
         hd.close()
+    return 0
+
+
+# ---------------------------------------------------------------- other modes
+
+def sample_rows(rp, n, budget_nnz):
+    """Rows 0-63 (the R-MAT hubs) plus 64 evenly spread blocks of consecutive
+    rows, sized so that the blocks hold about budget_nnz non-zeros."""
+    import numpy as np
+    deg = np.diff(rp)
+    B = int(max(16, budget_nnz / (64 * max(float(deg.mean()), 1.0))))
+    B = min(B, max(16, (n - 64) // 64))
+    starts = np.linspace(64, max(64, n - B), 64).astype(np.int64)
+    return np.unique(np.concatenate([np.arange(min(64, n))] + [np.arange(s0, min(n, s0 + B)) for s0 in starts]))
+
+
+def pinned_h2d_gbs(gib=1, reps=5):
+    """Host-to-device rate of a plain copy from pinned memory (the link)."""
+    import torch
+    src = torch.empty(gib << 28, dtype=torch.float32, pin_memory=True)
+    dst = torch.empty(gib << 28, dtype=torch.float32, device="cuda")
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src, non_blocking=True)
+    b.record()
+    torch.cuda.synchronize()
+    return (gib << 30) * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+
+def run_other_modes(args, modes) -> int:
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1602_02864_amd as pk
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    big = any(m in ("precision", "apps") for m in modes)
+    scale = args.scale if args.scale is not None else (26 if big else 25)
+    ef = args.edge_factor if args.edge_factor is not None else (28.0 if big else 44.0)
+    sym = big
+    t0 = time.perf_counter()
+    rp, col = synth.rmat_csr(scale, ef, seed=synth.SEED_GRAPH, symmetrize=sym, progress=log)
+    n, nnz = rp.shape[0] - 1, int(col.shape[0])
+    workload = f"rmat-s{scale}-ef{int(ef)}-{'symmetrised' if sym else 'directed'}"
+    log(f"graph {workload}: n={n} nnz={nnz} ({time.perf_counter() - t0:.1f}s)")
+    stream = torch.cuda.current_stream(dev)
+
+    def kernel_ms(h, fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        pk.spmm_timing_begin(h)
+        for _ in range(reps):
+            fn()
+        tot, runs = pk.spmm_timing_end(h)
+        return tot / max(runs, 1)
+
+    for mode in modes:
+        if mode == "stream":
+            ks = [int(x) for x in args.ks.split(",")]
+            link = pinned_h2d_gbs()
+            log(f"pinned host-to-device copy: {link:.1f} GB/s")
+            hd = pk.spmm_build_tiles(rp, col, validate=False)
+            hs = pk.spmm_build_tiles(rp, col, validate=False, place=pk.SPMM_PLACE_PINNED_HOST,
+                                     stream_kib=args.stream_kib, ring_depth=args.ring_depth)
+            payload = pk.spmm_get_stats(hs)["blob_bytes"]
+            copy = torch.cuda.Stream(dev)
+            per_k = {}
+            for k in ks:
+                X = torch.from_numpy(synth.uniform(n, k, seed=synth.SEED_X)).to(dev)
+                Yd = torch.empty((n, k), device=dev)
+                Ys = torch.empty((n, k), device=dev)
+                t_hbm = time_one(lambda: pk.spmm_run(hd, X, Yd, stream=stream))
+                t_str = time_one(lambda: pk.spmm_stream_run(hs, X, Ys, compute=stream, copy=copy))
+                torch.cuda.synchronize()
+                same = bool(torch.equal(Yd, Ys))
+                per_k[str(k)] = {"hbm_ms": round(t_hbm, 3), "stream_ms": round(t_str, 3),
+                                 "stream_gflops": round(2.0 * nnz * k / (t_str * 1e-3) / 1e9, 2),
+                                 "hbm_gflops": round(2.0 * nnz * k / (t_hbm * 1e-3) / 1e9, 2),
+                                 "payload_gbs": round(payload / (t_str * 1e-3) / 1e9, 2),
+                                 "link_frac": round(payload / (t_str * 1e-3) / 1e9 / link, 4),
+                                 "stream_over_hbm": round(t_hbm / t_str, 4),
+                                 "y_identical_to_hbm": same}
+                log(f"stream k={k}: {per_k[str(k)]}")
+                del X, Yd, Ys
+            tot_s = sum(v["stream_ms"] for v in per_k.values())
+            out = {"mode": "stream", "metric": "streamed SpMM GFLOP/s (A in pinned host memory) and % of host-to-device link",
+                   "value": round(sum(2.0 * nnz * k for k in ks) / (tot_s * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                   "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": workload, "n": n, "nnz": nnz, "k": ks,
+                              "stream_kib": args.stream_kib or 262144, "ring_depth": args.ring_depth or 3},
+                   "payload_bytes": int(payload), "link_gbs_measured": round(link, 2),
+                   "link_frac_min": min(v["link_frac"] for v in per_k.values()),
+                   "per_k": per_k}
+            print(json.dumps(out), flush=True)
+            hd.close()
+            hs.close()
+        elif mode == "precision":
+            vals = synth.lognormal_weights(rp, col, seed=synth.SEED_WEIGHT)
+            log("weights drawn")
+            sel = sample_rows(rp, n, 1.5e6)
+            tols = {"f32": 1e-6, "bf16": 1e-2, "fp8": 6e-2}
+            res = []
+            for weighted in (False, True):
+                h = pk.spmm_build_tiles(rp, col, vals if weighted else None, validate=False)
+                for k in (16, 32, 64):
+                    Xh = synth.uniform(n, k, seed=synth.SEED_X)
+                    X = torch.from_numpy(Xh).to(dev)
+                    Y = torch.empty((n, k), device=dev)
+                    ref = oracle.spmm_sel(rp, col, vals if weighted else None, Xh, sel)
+                    seld = torch.from_numpy(sel).to(dev)
+                    row = {"weighted": weighted, "k": k}
+                    for name, dt in (("f32", pk.SPMM_X_F32), ("bf16", pk.SPMM_X_BF16), ("fp8", pk.SPMM_X_FP8_E4M3)):
+                        cs = None
+                        if dt == pk.SPMM_X_F32:
+                            Xin = X
+                        elif dt == pk.SPMM_X_BF16:
+                            Xin = torch.empty((n, k), dtype=torch.bfloat16, device=dev)
+                            pk.spmm_quantize_x(X, Xin, dt)
+                        else:
+                            Xin = torch.empty((n, k), dtype=torch.uint8, device=dev)
+                            cs = torch.empty(k, dtype=torch.float32, device=dev)
+                            pk.spmm_quantize_x(X, Xin, dt, col_scale=cs)
+                        fn = (lambda Xin=Xin, dt=dt, cs=cs: pk.spmm_run(h, Xin, Y, dtype=dt, col_scale=cs, stream=stream))
+                        t = time_one(fn)
+                        tk = kernel_ms(h, fn)
+                        got = Y[seld].cpu().numpy()
+                        err = oracle.frob_rel_err(got, ref)
+                        row[name] = {"rel_frob_err": err, "tolerance": tols[name], "ok": err <= tols[name],
+                                     "ms": round(t, 3), "kernel_ms": round(tk, 3),
+                                     "gflops": round(2.0 * nnz * k / (t * 1e-3) / 1e9, 2)}
+                        del Xin
+                    log(f"precision {row}")
+                    res.append(row)
+                    del X, Y
+                h.close()
+            out = {"mode": "precision", "metric": "SpMM error vs the FP64 oracle (sampled rows) and GFLOP/s per X type",
+                   "n_gpus": 1, "data": "synthetic",
+                   "config": {"workload": workload, "n": n, "nnz": nnz, "weights": "binary and lognormal(0,1)",
+                              "sample_rows": int(sel.size), "sample_nnz": int(np.diff(rp)[sel].sum())},
+                   "all_ok": all(r[d]["ok"] for r in res for d in ("f32", "bf16", "fp8")), "results": res}
+            print(json.dumps(out), flush=True)
+        elif mode == "apps":
+            from paper_1602_02864_amd.selector_train import WEIGHTS
+            params = np.load(args.weights or WEIGHTS, allow_pickle=False).astype(np.float32)
+            out = {"mode": "apps", "metric": "PageRank and NMF time per iteration", "n_gpus": 1,
+                   "data": "synthetic", "config": {"workload": workload, "n": n, "nnz": nnz}}
+            for sel_name in ("plain", "learned"):
+                h = pk.spmm_build_tiles(rp, col, validate=False)
+                if sel_name == "learned":
+                    pk.spmm_select_learned(h, params, 1)
+                pr = torch.empty(n, device=dev)
+                pk.spmm_pagerank(h, pr, iters=2)   # warm-up (upload, graph build)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                resid = pk.spmm_pagerank(h, pr, iters=30)
+                t_pr = time.perf_counter() - t0
+                s_pr = float(pr.double().sum().item())
+                t_spmv = kernel_ms(h, lambda: pk.spmm_run(h, pr[:, None], torch.empty((n, 1), device=dev),
+                                                          stream=stream))
+                if sel_name == "learned":
+                    pk.spmm_select_learned(h, params, 16)
+                W = torch.from_numpy(synth.uniform(n, 16, seed=synth.SEED_W)).to(dev)
+                Hm = torch.from_numpy(synth.uniform(n, 16, seed=synth.SEED_H)).to(dev)
+                pk.spmm_nmf(h, h, W, Hm, iters=1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pk.spmm_nmf(h, h, W, Hm, iters=10)
+                torch.cuda.synchronize()
+                t_nmf = time.perf_counter() - t0
+                ok_nmf = bool(torch.isfinite(W).all().item() and torch.isfinite(Hm).all().item()
+                              and (W >= 0).all().item() and (Hm >= 0).all().item())
+                out[sel_name] = {
+                    "pagerank_ms_per_iter": round(t_pr * 1e3 / 30, 3),
+                    "pagerank_spmv_gflops": round(2.0 * nnz / (t_spmv * 1e-3) / 1e9, 2),
+                    "pagerank_sum": s_pr, "pagerank_resid_first_last": [float(resid[0]), float(resid[-1])],
+                    "nmf_ms_per_iter": round(t_nmf * 1e3 / 10, 3),
+                    "nmf_spmm_gflops": round(2 * 2.0 * nnz * 16 / (t_nmf / 10) / 1e9, 2),
+                    "nmf_factors_finite_nonneg": ok_nmf}
+                log(f"apps {sel_name}: {out[sel_name]}")
+                del W, Hm, pr
+                h.close()
+            out["learned_over_plain_pagerank"] = round(out["plain"]["pagerank_ms_per_iter"] /
+                                                       out["learned"]["pagerank_ms_per_iter"], 4)
+            out["learned_over_plain_nmf"] = round(out["plain"]["nmf_ms_per_iter"] / out["learned"]["nmf_ms_per_iter"], 4)
+            print(json.dumps(out), flush=True)
+        else:
+            raise SystemExit(f"unknown mode {mode}")
     return 0
 
 

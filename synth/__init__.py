@@ -72,12 +72,13 @@ def _ptr(a: np.ndarray) -> int:
 
 
 def rmat_csr(scale: int, edge_factor: float, seed: int = SEED_GRAPH, symmetrize: bool = False,
-             a: float = RMAT_A, b: float = RMAT_B, c: float = RMAT_C):
+             a: float = RMAT_A, b: float = RMAT_B, c: float = RMAT_C, progress=None):
     """R-MAT adjacency matrix as CSR (row_ptr int64[n+1], col int32[nnz]).
 
     ``edge_factor * 2**scale`` samples are drawn; self-loops are removed, the
     pattern is symmetrised when asked, and duplicates are removed, so the
     returned nnz is the post-dedup count.  Columns are sorted within rows.
+    ``progress(msg)``, if given, is called after each of the two phases.
     """
     L = _load()
     nsamples = int(round(edge_factor * (1 << scale)))
@@ -88,9 +89,13 @@ def rmat_csr(scale: int, edge_factor: float, seed: int = SEED_GRAPH, symmetrize:
                             ctypes.byref(h), ctypes.byref(n), ctypes.byref(nnz))
     if rc != 0:
         raise MemoryError("synth_rmat_begin failed")
+    if progress:
+        progress(f"R-MAT scale {scale}: {nsamples} samples drawn and bucketed by row")
     row_ptr = np.empty(n.value + 1, dtype=np.int64)
     col = np.empty(max(nnz.value, 1), dtype=np.int32)[: nnz.value]
     L.synth_rmat_finish(h, _ptr(row_ptr), _ptr(col) if nnz.value else _ptr(np.empty(1, np.int32)))
+    if progress:
+        progress(f"R-MAT scale {scale}: rows sorted and deduplicated, nnz {col.shape[0]}")
     return row_ptr, col
 
 

@@ -183,3 +183,38 @@ def test_learned_selection_follows_model(small_graph):
     assert np.all(chosen <= ref.min(axis=1) + 1e-4 * (1 + np.abs(ref.min(axis=1))))
     _check_exact(hd, rp, col, n)
     hd.close()
+
+
+def test_trained_selector_gain_on_held_out_graph():
+    """What the shipped cost model gains over single fixed formats.
+
+    On a graph none of the training graphs used (scale 18, seed 17), for
+    several k, every bucket of tiles is timed in every variant; the regret of
+    a choice is its bucket-model time over the per-bucket optimum (the
+    exhaustive autotuner).  The learned choice must stay close to that
+    optimum and beat every single fixed format, averaged over the settings.
+    """
+    import torch
+    from paper_1602_02864_amd.selector_train import WEIGHTS
+    params = np.load(WEIGHTS, allow_pickle=False).astype(np.float32)
+    rp, col = synth.rmat_csr(18, 16, seed=17)
+    hd = pk.spmm_build_tiles(rp, col, validate=False)
+    pd = torch.from_numpy(params).to(dev())
+    regret = {"learned": [], **{name: [] for name in pk.VARIANT_NAMES}}
+    for k in (1, 4, 16, 32):
+        b, ns = pk.spmm_selector_collect(hd, k, reps=7)
+        f = torch.from_numpy(pk.spmm_tile_features(hd, k)).to(dev())
+        ch = torch.empty(f.shape[0], dtype=torch.uint8, device=dev())
+        pk.spmm_mlp_predict(pd, f, None, ch)
+        torch.cuda.synchronize()
+        c = ch.cpu().numpy().astype(np.int64)
+        best = ns.min(axis=1)[b].sum()
+        regret["learned"].append(ns[b, c].sum() / best - 1.0)
+        for v, name in enumerate(pk.VARIANT_NAMES):
+            regret[name].append(ns[b, v].sum() / best - 1.0)
+    hd.close()
+    mean = {a: float(np.mean(r)) for a, r in regret.items()}
+    print("mean regret over the per-bucket optimum:", {a: round(m, 4) for a, m in mean.items()})
+    assert mean["learned"] <= 0.05
+    assert max(regret["learned"]) <= 0.10
+    assert mean["learned"] < min(mean[name] for name in pk.VARIANT_NAMES)
