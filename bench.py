@@ -99,6 +99,26 @@ def time_step(runs, steps, warmup, stream):
     return wall * 1e3 / steps, ms_k
 
 
+def attainable_read_gbs(gib=16, reps=5):
+    """Read rate of a plain streaming-read kernel over gib GiB (the HBM rate a
+    simple kernel attains on this machine, beside the 8 TB/s nominal)."""
+    import torch
+
+    import paper_1602_02864_amd as pk
+    buf = torch.ones(gib << 28, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    pk.spmm_read_probe(buf, sink)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        pk.spmm_read_probe(buf, sink)
+    b.record()
+    torch.cuda.synchronize()
+    del buf
+    return (gib << 30) * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+
 def time_one(fn, reps=3):
     import torch
     fn()
@@ -299,13 +319,17 @@ def main() -> int:
     launch_bytes = mb["A"] + C * kc * 4 + n * kc * 4
     launch_ms = kernel_ms[kdom] / launches
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    read_gbs = attainable_read_gbs()
+    log(f"attainable streaming read: {read_gbs:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kc),
                 "kernel": f"spmm_items k={kdom} (kc={kc}, {launches} launch(es) per SpMM; "
                           f"duration from HIP events around the launches)",
                 "bytes_per_launch": int(launch_bytes), "ms_per_launch": round(launch_ms, 4),
-                "kernel_source_sha256_16": kernel_source_hash()}
+                "kernel_source_sha256_16": kernel_source_hash(),
+                "attainable_read_gbs": round(read_gbs, 1),
+                "frac_of_attainable": round(achieved / read_gbs, 4)}
 
     compare = None
     if args.compare:
@@ -323,6 +347,13 @@ def main() -> int:
             compare["autotune_s"][str(k)] = round(time.perf_counter() - t0, 1)
             compare["autotune"][str(k)] = round(time_one(lambda: pk.spmm_run(hc, Xs[k], Ys[k], stream=stream)), 4)
             log(f"autotune k={k}: {compare['autotune'][str(k)]} ms ({compare['autotune_s'][str(k)]}s)")
+        # ablation: tiles over the original column order (no in-degree relabelling)
+        hk = pk.spmm_build_tiles(rp, col, tile_rows=args.tile_rows, tile_cols=args.tile_cols,
+                                 item_nnz=args.item_nnz, max_kc=args.max_kc, validate=False, keep_order=True)
+        compare["ablation_original_column_order"] = {str(k): round(time_one(
+            lambda k=k: pk.spmm_run(hk, Xs[k], Ys[k], stream=stream)), 4) for k in ks}
+        log(f"original column order: {compare['ablation_original_column_order']}")
+        hk.close()
         compare["learned"] = {}
         for k in ks:
             pk.spmm_select_learned(hc, params, k)

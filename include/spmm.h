@@ -256,6 +256,16 @@ spmm_status_t spmm_decode_tiles(spmm_handle_t h, int64_t* row_ptr, int32_t* col_
 spmm_status_t spmm_timing_begin(spmm_handle_t h);
 spmm_status_t spmm_timing_end(spmm_handle_t h, double* total_ms, uint64_t* n_runs);
 
+/*
+ * Measurement utility: one streaming read of `bytes` of device memory at
+ * `buf` (16-byte aligned, a multiple of 16) with 16-byte loads, asynchronous
+ * on s.  `sink` (device float[1]) is written only for a sum no all-ones or
+ * all-zeros buffer produces.  Timed by the caller, it gives the HBM read
+ * rate a plain kernel attains, the context for the SpMM's roofline.
+ * Errors: SPMM_EINVAL (NULL, misaligned), SPMM_EHIP.
+ */
+spmm_status_t spmm_read_probe(const void* buf, uint64_t bytes, float* sink, hipStream_t s);
+
 /* Shape and storage statistics of a handle. */
 typedef struct {
     uint64_t n_rows, n_cols, nnz;

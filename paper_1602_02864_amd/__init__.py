@@ -134,6 +134,7 @@ def load_library():
             ("spmm_selector_train", [vp, vp, vp, i64, ctypes.POINTER(spmm_train_opts), vp, vp]),
             ("spmm_select_learned", [vp, vp, i32, i32]),
             ("spmm_timing_begin", [vp]),
+            ("spmm_read_probe", [vp, ctypes.c_uint64, vp, vp]),
             ("spmm_timing_end", [vp, vp, vp])]:
         fn = getattr(L, name)
         fn.restype = i32
@@ -306,6 +307,13 @@ def spmm_nmf(hA: Handle, hAT: Handle, W, H, iters: int = 10, eps: float = 1e-9, 
     st = load_library().spmm_nmf(hA.ptr, hAT.ptr, int(W.shape[1]), int(iters), float(eps), _ptr(W), _ptr(H),
                                  _stream(stream, W))
     _check(st, "spmm_nmf")
+
+
+def spmm_read_probe(buf, sink, nbytes: int | None = None, stream=None) -> None:
+    """One streaming read of a device buffer (bandwidth measurement)."""
+    nbytes = buf.numel() * buf.element_size() if nbytes is None else int(nbytes)
+    st = load_library().spmm_read_probe(_ptr(buf), nbytes, _ptr(sink), _stream(stream, buf))
+    _check(st, "spmm_read_probe")
 
 
 def spmm_timing_begin(h: Handle) -> None:

@@ -180,33 +180,48 @@ spmm_status_t ensure_xperm(spmm::Handle& H, uint64_t need) {
 // otherwise (and if the handle relabels columns) X is first gathered into a
 // handle-owned buffer in that order.  Buffers must already exist when this
 // runs under stream capture (it allocates only when X needs gathering).
-spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt, const float* col_scale,
-                         float* Y, int64_t ldy, hipStream_t s, bool x_in_handle_order) {
-    spmm::RunArgs a{};
+// X for the SpMM launches of one run: gathered into the handle's column
+// order when the handle relabels columns and X is not already in that order
+// (rows of 1 or 2 elements stay dense; wider rows are padded to a multiple
+// of 4 elements so that they can be read as 16-byte vectors), and the
+// fixed-point exponents taken from the values read.
+spmm_status_t prepare_x(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt, hipStream_t s,
+                        bool x_in_handle_order, spmm::RunArgs& a) {
     a.X = X;
     a.k = k;
     a.ldx = ldx;
+    const int32_t* perm = nullptr;
+    void* Xp = nullptr;
+    int64_t ldp = ldx;
     if (H.relabel && H.n_cols > 0 && !x_in_handle_order) {
         const int esize = dt == SPMM_X_F32 ? 4 : dt == SPMM_X_BF16 ? 2 : 1;
-        const int64_t ldp = (k + 3) / 4 * 4;
+        ldp = k <= 2 ? k : (k + 3) / 4 * 4;
         spmm_status_t st = ensure_xperm(H, (uint64_t)H.n_cols * ldp * esize);
         if (st != SPMM_OK) return st;
-        hipError_t pe = spmm::launch_permute_rows(X, ldx, k, esize, H.d_col_old, H.n_cols, H.d_xperm, ldp, s);
-        if (pe != hipSuccess) return hip_fail(pe, "X permutation launch");
-        a.X = H.d_xperm;
+        perm = H.d_col_old;
+        Xp = H.d_xperm;
+    }
+    hipError_t e = spmm::launch_prepare_x(X, dt, ldx, k, perm, H.n_cols, Xp, ldp, H.max_row_l1, H.d_colmax,
+                                          H.d_fexp, s);
+    if (e != hipSuccess) return hip_fail(e, "X preparation launch");
+    if (Xp) {
+        a.X = Xp;
         a.ldx = ldp;
     }
+    a.fexp = H.d_fexp;
+    return SPMM_OK;
+}
+
+spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt, const float* col_scale,
+                         float* Y, int64_t ldy, hipStream_t s, bool x_in_handle_order) {
+    spmm::RunArgs a{};
+    spmm_status_t st = prepare_x(H, X, k, ldx, dt, s, x_in_handle_order, a);
+    if (st != SPMM_OK) return st;
     a.dtype = dt;
     a.col_scale = col_scale;
     a.Y = Y;
     a.ldy = ldy;
     a.stream = s;
-    {
-        hipError_t fe = spmm::launch_fixed_exponents(a.X, dt, H.n_cols, k, a.ldx, H.max_row_l1, H.d_colmax,
-                                                     H.d_fexp, s);
-        if (fe != hipSuccess) return hip_fail(fe, "fixed-point scale launch");
-    }
-    a.fexp = H.d_fexp;
     a.blob = static_cast<const uint8_t*>(H.d_blob);
     a.blob_bias = 0;
     a.items = H.d_items;
@@ -368,29 +383,12 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
             }
         }
         spmm::RunArgs a{};
-        a.X = X;
-        a.k = k;
-        a.ldx = ldx;
-        if (H.relabel && H.n_cols > 0) {
-            const int esize = dt == SPMM_X_F32 ? 4 : dt == SPMM_X_BF16 ? 2 : 1;
-            const int64_t ldp = (k + 3) / 4 * 4;
-            if ((st = ensure_xperm(H, (uint64_t)H.n_cols * ldp * esize)) != SPMM_OK) return st;
-            hipError_t pe = spmm::launch_permute_rows(X, ldx, k, esize, H.d_col_old, H.n_cols, H.d_xperm, ldp, compute);
-            if (pe != hipSuccess) return hip_fail(pe, "X permutation launch");
-            a.X = H.d_xperm;
-            a.ldx = ldp;
-        }
+        if ((st = prepare_x(H, X, k, ldx, dt, compute, false, a)) != SPMM_OK) return st;
         a.dtype = dt;
         a.col_scale = col_scale;
         a.Y = Y;
         a.ldy = ldy;
         a.stream = compute;
-        {
-            hipError_t fe = spmm::launch_fixed_exponents(a.X, dt, H.n_cols, k, a.ldx, H.max_row_l1, H.d_colmax,
-                                                         H.d_fexp, compute);
-            if (fe != hipSuccess) return hip_fail(fe, "fixed-point scale launch");
-        }
-        a.fexp = H.d_fexp;
         a.combine = H.d_combine;
         a.n_combine = (uint32_t)H.enc.combine.size();
         a.count = H.d_count;
@@ -565,6 +563,14 @@ spmm_status_t spmm_quantize_x(const float* X, int64_t n, int k, int64_t ldx, spm
     hipError_t e = spmm::launch_quantize(X, n, k, ldx, dt, Xq, ldq, col_scale,
                                          (flags & SPMM_QUANT_SCALES_GIVEN) != 0, s);
     return e == hipSuccess ? SPMM_OK : hip_fail(e, "quantize launch");
+}
+
+spmm_status_t spmm_read_probe(const void* buf, uint64_t bytes, float* sink, hipStream_t s) {
+    if (!buf || !sink) return fail(SPMM_EINVAL, "NULL argument");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(buf) % 16)
+        return fail(SPMM_EINVAL, "buf and bytes must be multiples of 16");
+    hipError_t e = spmm::launch_read_probe(buf, bytes, sink, s);
+    return e == hipSuccess ? SPMM_OK : hip_fail(e, "read probe launch");
 }
 
 spmm_status_t spmm_timing_begin(spmm_handle_t h) {

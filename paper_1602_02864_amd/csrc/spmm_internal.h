@@ -201,13 +201,15 @@ struct RunArgs {
     const int32_t* fexp;         // device, per column of X: fixed-point exponent
 };
 hipError_t launch_spmm(const Handle& H, const RunArgs& a);
-// Per-column fixed-point exponents for the accumulators: with M_j = max |x_j|
-// and R = max row L1 norm of A, f_j = 61 - e_j where R M_j < 2^e_j, so every
-// partial sum of a row, scaled by 2^f_j, stays below 2^61 in magnitude.
-hipError_t launch_fixed_exponents(const void* X, int dtype, int64_t n, int k, int64_t ldx, double row_l1,
-                                  uint32_t* colmax, int32_t* fexp, hipStream_t s);
-hipError_t launch_permute_rows(const void* X, int64_t ldx, int k, int esize, const int32_t* old_of_new,
-                               int64_t n, void* Xp, int64_t ldp, hipStream_t s);
+// X prepared for a launch: optionally gathered into the handle's column
+// order (Xp row i = X row old_of_new[i], row stride ldp; Xp NULL = read in
+// place), and the per-column fixed-point exponents of the accumulators:
+// with M_j = max |x_j| and R = max row L1 norm of A, f_j = 61 - e_j where
+// R M_j < 2^e_j, so every partial sum of a row, scaled by 2^f_j, stays below
+// 2^61 in magnitude.
+hipError_t launch_prepare_x(const void* X, int dtype, int64_t ldx, int k, const int32_t* old_of_new, int64_t n,
+                            void* Xp, int64_t ldp, double row_l1, uint32_t* colmax, int32_t* fexp,
+                            hipStream_t s);
 
 // apps_kernels.hip
 hipError_t launch_pr_init(float* pr, int64_t n, float v, hipStream_t s);
@@ -232,6 +234,9 @@ hipError_t launch_mlp_grad(const float* params, const float* feat, const float* 
                            hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int np, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
+
+// probe_kernels.hip: one streaming read of bytes (a multiple of 16) at buf
+hipError_t launch_read_probe(const void* buf, uint64_t bytes, float* sink, hipStream_t s);
 
 // quant_kernels.hip
 hipError_t launch_quantize(const float* X, int64_t n, int k, int64_t ldx, int dtype, void* Xq,

@@ -369,30 +369,6 @@ __global__ __launch_bounds__(256) void spmm_items(
     if (lane == 0) atomicExch(&count[d.cid], 0u);
 }
 
-// Column absmax of X as stored (decoded to FP32; |x| compared as FP32 bits).
-template <typename XT>
-__global__ __launch_bounds__(256) void colmax_kernel(const XT* __restrict__ X, int64_t n, int k, int64_t ldx,
-                                                     uint32_t* __restrict__ m) {
-    __shared__ uint32_t red[64];
-    const int per_block = (256 / k) * k;
-    if (threadIdx.x < 64) red[threadIdx.x] = 0u;
-    __syncthreads();
-    if ((int)threadIdx.x < per_block) {
-        const int j = threadIdx.x % k;
-        uint32_t best = 0u;
-        const int64_t rows_per_step = (int64_t)gridDim.x * (per_block / k);
-        for (int64_t i = (int64_t)blockIdx.x * (per_block / k) + threadIdx.x / k; i < n; i += rows_per_step) {
-            float v[1];
-            XLd<XT, 1>::load(X + i * ldx + j, v);
-            const uint32_t b = __float_as_uint(v[0]) & 0x7FFFFFFFu;
-            best = b > best ? b : best;
-        }
-        atomicMax(&red[j], best);
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < k) atomicMax(&m[threadIdx.x], red[threadIdx.x]);
-}
-
 __global__ void colmax_init_kernel(uint32_t* m) {
     if (threadIdx.x < 64) m[threadIdx.x] = 0u;
 }
@@ -479,57 +455,99 @@ hipError_t launch_typed(const Handle& H, const RunArgs& a) {
     return hipSuccess;
 }
 
-// Xp[i, :] = X[old_of_new[i], :] (the relabelled column order).  Lanes run
-// across (row, column) pairs, so writes are coalesced and each source row is
-// read as one contiguous piece.
-template <typename T>
-__global__ __launch_bounds__(256) void permute_rows(const T* __restrict__ X, int64_t ldx, int k,
-                                                    const int32_t* __restrict__ old_of_new,
-                                                    int64_t n, T* __restrict__ Xp, int64_t ldp) {
-    const int64_t total = n * k;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = t / k;
-        const int j = (int)(t - i * k);
-        Xp[i * ldp + j] = X[(int64_t)old_of_new[i] * ldx + j];
+// X rows into the handle's column order (Xp row i = X row old_of_new[i]),
+// together with the per-column max |x| of the values read (decoded to FP32,
+// compared as FP32 bits with integer atomicMax: exact and order-free).  With
+// Xp NULL nothing is written and rows are read in place.  One thread moves
+// one U-sized unit (E elements) of a row; 2^lsh lanes cover a row's units
+// and keep the same lane -> unit mapping for every row they visit, so each
+// thread holds a running max for the same E columns throughout.
+template <typename U, typename XT>
+__global__ __launch_bounds__(256) void gather_colmax_kernel(const XT* __restrict__ X, int64_t ldx,
+                                                            const int32_t* __restrict__ old_of_new, int64_t n,
+                                                            int k, XT* __restrict__ Xp, int64_t ldp, int lsh,
+                                                            uint32_t* __restrict__ m) {
+    constexpr int E = sizeof(U) / sizeof(XT);
+    __shared__ uint32_t red[64];
+    if (threadIdx.x < 64) red[threadIdx.x] = 0u;
+    __syncthreads();
+    const int units = k / E;
+    const int u = threadIdx.x & ((1 << lsh) - 1);
+    if (u < units) {
+        uint32_t best[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) best[q] = 0u;
+        const int64_t step = ((int64_t)gridDim.x * blockDim.x) >> lsh;
+        for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lsh; i < n; i += step) {
+            const int64_t src = old_of_new ? (int64_t)old_of_new[i] : i;
+            const U v = *reinterpret_cast<const U*>(X + src * ldx + (int64_t)u * E);
+            if (Xp) *reinterpret_cast<U*>(Xp + i * ldp + (int64_t)u * E) = v;
+            const XT* e = reinterpret_cast<const XT*>(&v);
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                float f[1];
+                XLd<XT, 1>::load(e + q, f);
+                const uint32_t bits = __float_as_uint(f[0]) & 0x7FFFFFFFu;
+                best[q] = bits > best[q] ? bits : best[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) atomicMax(&red[u * E + q], best[q]);
     }
+    __syncthreads();
+    if ((int)threadIdx.x < k) atomicMax(&m[threadIdx.x], red[threadIdx.x]);
+}
+
+template <typename U, typename XT>
+void launch_gather_unit(const XT* X, int64_t ldx, const int32_t* old_of_new, int64_t n, int k, XT* Xp,
+                        int64_t ldp, uint32_t* m, hipStream_t s) {
+    constexpr int E = sizeof(U) / sizeof(XT);
+    const int units = k / E;
+    int lsh = 0;
+    while ((1 << lsh) < units) ++lsh;
+    const int64_t rows_per_block = 256 >> lsh;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (n + rows_per_block - 1) / rows_per_block));
+    hipLaunchKernelGGL((gather_colmax_kernel<U, XT>), dim3(blocks), dim3(256), 0, s, X, ldx, old_of_new, n, k, Xp,
+                       ldp, lsh, m);
+}
+
+// The widest unit (16, 8, 4, 2 or 1 bytes) that divides every row offset
+// and both base addresses.
+template <typename XT>
+void launch_gather(const XT* X, int64_t ldx, const int32_t* old_of_new, int64_t n, int k, XT* Xp, int64_t ldp,
+                   uint32_t* m, hipStream_t s) {
+    auto fits = [&](size_t ub) {
+        const size_t es = sizeof(XT);
+        if (ub < es || ((size_t)k * es) % ub || ((size_t)ldx * es) % ub || reinterpret_cast<uintptr_t>(X) % ub)
+            return false;
+        return !Xp || (((size_t)ldp * es) % ub == 0 && reinterpret_cast<uintptr_t>(Xp) % ub == 0);
+    };
+    if (fits(16)) return launch_gather_unit<uint4, XT>(X, ldx, old_of_new, n, k, Xp, ldp, m, s);
+    if (fits(8)) return launch_gather_unit<uint2, XT>(X, ldx, old_of_new, n, k, Xp, ldp, m, s);
+    if (fits(4)) return launch_gather_unit<uint32_t, XT>(X, ldx, old_of_new, n, k, Xp, ldp, m, s);
+    if constexpr (sizeof(XT) <= 2)
+        if (fits(2)) return launch_gather_unit<uint16_t, XT>(X, ldx, old_of_new, n, k, Xp, ldp, m, s);
+    if constexpr (sizeof(XT) == 1) return launch_gather_unit<uint8_t, XT>(X, ldx, old_of_new, n, k, Xp, ldp, m, s);
 }
 
 }  // namespace
 
-hipError_t launch_fixed_exponents(const void* X, int dtype, int64_t n, int k, int64_t ldx, double row_l1,
-                                  uint32_t* colmax, int32_t* fexp, hipStream_t s) {
+hipError_t launch_prepare_x(const void* X, int dtype, int64_t ldx, int k, const int32_t* old_of_new, int64_t n,
+                            void* Xp, int64_t ldp, double row_l1, uint32_t* colmax, int32_t* fexp,
+                            hipStream_t s) {
     hipLaunchKernelGGL(colmax_init_kernel, dim3(1), dim3(64), 0, s, colmax);
     if (n > 0) {
-        const unsigned blocks = (unsigned)std::min<int64_t>(2048, (n + 3) / 4);
         if (dtype == SPMM_X_BF16)
-            hipLaunchKernelGGL(colmax_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s,
-                               static_cast<const uint16_t*>(X), n, k, ldx, colmax);
+            launch_gather(static_cast<const uint16_t*>(X), ldx, old_of_new, n, k, static_cast<uint16_t*>(Xp), ldp,
+                          colmax, s);
         else if (dtype == SPMM_X_FP8_E4M3)
-            hipLaunchKernelGGL(colmax_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s,
-                               static_cast<const uint8_t*>(X), n, k, ldx, colmax);
+            launch_gather(static_cast<const uint8_t*>(X), ldx, old_of_new, n, k, static_cast<uint8_t*>(Xp), ldp,
+                          colmax, s);
         else
-            hipLaunchKernelGGL(colmax_kernel<float>, dim3(blocks), dim3(256), 0, s,
-                               static_cast<const float*>(X), n, k, ldx, colmax);
+            launch_gather(static_cast<const float*>(X), ldx, old_of_new, n, k, static_cast<float*>(Xp), ldp, colmax,
+                          s);
     }
     hipLaunchKernelGGL(fexp_kernel, dim3(1), dim3(64), 0, s, colmax, k, row_l1, fexp);
-    return hipGetLastError();
-}
-
-hipError_t launch_permute_rows(const void* X, int64_t ldx, int k, int esize, const int32_t* old_of_new,
-                               int64_t n, void* Xp, int64_t ldp, hipStream_t s) {
-    const int64_t total = n * k;
-    if (!total) return hipSuccess;
-    const unsigned blocks = (unsigned)std::min<int64_t>(65536, (total + 255) / 256);
-    if (esize == 4)
-        hipLaunchKernelGGL(permute_rows<uint32_t>, dim3(blocks), dim3(256), 0, s,
-                           static_cast<const uint32_t*>(X), ldx, k, old_of_new, n, static_cast<uint32_t*>(Xp), ldp);
-    else if (esize == 2)
-        hipLaunchKernelGGL(permute_rows<uint16_t>, dim3(blocks), dim3(256), 0, s,
-                           static_cast<const uint16_t*>(X), ldx, k, old_of_new, n, static_cast<uint16_t*>(Xp), ldp);
-    else
-        hipLaunchKernelGGL(permute_rows<uint8_t>, dim3(blocks), dim3(256), 0, s,
-                           static_cast<const uint8_t*>(X), ldx, k, old_of_new, n, static_cast<uint8_t*>(Xp), ldp);
     return hipGetLastError();
 }
 

@@ -147,3 +147,22 @@ def test_model_tiles_and_paper_formula(t):
     # S_SCSR / S_DCSC within the paper's bound when nnr ~ nnc (symmetric A)
     r = oracle.scsr_bytes(R, col.shape[0], 0) / oracle.dcsc_bytes(C, col.shape[0], 0)
     assert 0.4 <= r < 1.0 or R != C
+
+
+def test_timing_window_without_runs():
+    rp, col = synth.small_random_csr(50, 0.1, 3)
+    h = pk.spmm_build_tiles(rp, col)
+    pk.spmm_timing_begin(h)
+    assert pk.spmm_timing_end(h) == (0.0, 0)
+    assert pk.spmm_timing_end(h) == (0.0, 0)   # ending again: still empty
+    h.close()
+    L = pk.load_library()
+    assert L.spmm_timing_begin(None) == pk.SPMM_EINVAL
+    assert L.spmm_timing_end(None, None, None) == pk.SPMM_EINVAL
+
+
+def test_read_probe_rejects_bad_arguments():
+    L = pk.load_library()
+    assert L.spmm_read_probe(None, 16, None, None) == pk.SPMM_EINVAL
+    assert L.spmm_read_probe(16, 15, 16, None) == pk.SPMM_EINVAL     # not a multiple of 16
+    assert L.spmm_read_probe(8, 16, 16, None) == pk.SPMM_EINVAL      # misaligned

@@ -9,7 +9,7 @@ import pytest
 import oracle
 import paper_1602_02864_amd as pk
 import synth
-from gpu_util import run_spmm
+from gpu_util import dev, run_spmm
 
 pytestmark = pytest.mark.gpu
 
@@ -140,3 +140,32 @@ def test_hub_rows_fp32_accuracy():
     assert oracle.frob_rel_err(Y, ref) <= 1e-6
     top = np.argsort(np.diff(rp))[-50:]
     assert oracle.frob_rel_err(Y[top], ref[top]) <= 1e-6
+
+
+def test_kernel_timing_counts_runs(graph):
+    import torch
+    rp, col = graph
+    n = rp.shape[0] - 1
+    h = pk.spmm_build_tiles(rp, col)
+    X = torch.from_numpy(synth.uniform(n, 4, seed=2)).to(dev())
+    Y = torch.empty((n, 4), device=dev())
+    pk.spmm_run(h, X, Y)
+    pk.spmm_timing_begin(h)
+    for _ in range(3):
+        pk.spmm_run(h, X, Y)
+    ms, runs = pk.spmm_timing_end(h)
+    assert runs == 3 and ms > 0.0
+    pk.spmm_run(h, X, Y)            # after the window: not recorded
+    pk.spmm_timing_begin(h)
+    assert pk.spmm_timing_end(h) == (0.0, 0)
+    h.close()
+
+
+def test_read_probe_reads_without_writing():
+    import torch
+    buf = torch.ones(1 << 20, dtype=torch.float32, device=dev())
+    sink = torch.full((1,), 7.0, device=dev())
+    pk.spmm_read_probe(buf, sink)
+    pk.spmm_read_probe(buf[:5], sink, nbytes=16)   # a partial buffer
+    torch.cuda.synchronize()
+    assert sink.item() == 7.0
