@@ -106,6 +106,11 @@ typedef struct {
                                  group, KiB; 0 -> 262144 (256 MiB)                 */
     uint32_t ring_depth;     /* streamed mode: device slots in the transfer ring;
                                  0 -> 3; 2..16                                    */
+    int32_t x_stage_kib;     /* launches of <= 8 X columns: > 0 stages the
+                                 hottest X rows in this many KiB of LDS per
+                                 workgroup (a persistent launch, one workgroup
+                                 per CU; capped by the device's LDS); <= 0 -> no
+                                 staging (the default: measured faster)          */
 } spmm_build_opts;
 
 typedef struct spmm_handle_s* spmm_handle_t;

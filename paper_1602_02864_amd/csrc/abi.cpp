@@ -318,6 +318,7 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         H.relabel = o.keep_order == 0;
         H.stream_bytes = (uint64_t)(o.stream_kib ? o.stream_kib : 262144u) << 10;
         H.ring_depth = o.ring_depth ? o.ring_depth : 3u;
+        H.stage_bytes = o.x_stage_kib > 0 ? (uint64_t)o.x_stage_kib << 10 : 0u;
         if (H.ring_depth < 2 || H.ring_depth > 16) return fail(SPMM_EINVAL, "ring_depth must be in 2..16");
         std::string err;
         spmm_status_t st = spmm::build_canonical(H, row_ptr, col_idx, values, o.validate != 0, err);

@@ -115,6 +115,7 @@ void make_subset(const spmm::Handle& H, const std::vector<uint64_t>& sel, spmm::
     S.n_strips = H.n_strips;
     S.max_row_l1 = H.max_row_l1;
     S.max_kc = H.max_kc;
+    S.stage_bytes = H.stage_bytes;
     S.relabel = false;
     uint64_t nnz = 0;
     for (uint64_t t : sel) nnz += H.tiles[t].nnz;

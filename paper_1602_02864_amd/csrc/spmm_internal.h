@@ -140,6 +140,7 @@ struct Handle {
     uint32_t* d_count = nullptr;  // per split slab: items finished in this launch
     uint64_t part_cap = 0;
     int max_kc = 16;              // widest column chunk per launch (16 or 32)
+    uint64_t stage_bytes = 0;     // LDS per workgroup for staged X rows (0 = none)
     // streamed mode: item groups copied host -> device ring per SpMM
     struct Group {
         uint64_t i0, i1;          // items

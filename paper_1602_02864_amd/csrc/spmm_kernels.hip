@@ -6,7 +6,9 @@
 // Algorithm 1, which merges every tile product of a tile row locally and
 // writes each output row once.  A workgroup holds up to four independent
 // wavefronts (four items); the wavefronts never synchronise with each
-// other.
+// other.  On request (a build option), launches of at most 8 columns use a
+// persistent form instead: one workgroup per CU stages the hottest rows of
+// X in LDS once, and its wavefronts then loop over the items.
 //
 // Within an item the entries arrive in three streams, each with its own
 // mapping onto the 64 lanes (G = KC / VW lanes cover the KC columns of one
@@ -132,24 +134,42 @@ __device__ __forceinline__ float from_fixed(unsigned long long q, int32_t f) {
     return (float)ldexp((double)(long long)q, -f);
 }
 
-template <int KC, int VW, typename XT, bool HV>
-__global__ __launch_bounds__(256) void spmm_items(
-    const ItemDesc* __restrict__ items, uint32_t n_items, const uint8_t* __restrict__ blob,
-    uint64_t blob_bias, const XT* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
-    int64_t* __restrict__ part, const CombineDesc* __restrict__ combine,
-    uint32_t* __restrict__ count, const float* __restrict__ yscale, const int32_t* __restrict__ fexp,
-    uint32_t h, uint32_t wshift, int64_t n_rows) {
+// X[gc, c0 .. c0 + VW) as FP32: from the rows staged in LDS (ns rows of KC
+// decoded values) when gc is one of them, else from memory.
+template <typename XT, int KC, int VW, bool STAGED>
+__device__ __forceinline__ void xget(const XT* __restrict__ X, int64_t ldx, int c0, int64_t gc,
+                                     const float* xs, uint32_t ns, float* v) {
+    if constexpr (STAGED) {
+        if (gc < (int64_t)ns) {
+            const float* p = xs + gc * KC + c0;
+            if constexpr (VW == 4) {
+                const float4 t = *reinterpret_cast<const float4*>(p);
+                v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+            } else if constexpr (VW == 2) {
+                const float2 t = *reinterpret_cast<const float2*>(p);
+                v[0] = t.x; v[1] = t.y;
+            } else {
+                v[0] = p[0];
+            }
+            return;
+        }
+    }
+    XLd<XT, VW>::load(X + gc * ldx + c0, v);
+}
+
+// One work item on one wavefront (see the file comment); acc is the
+// wavefront's h x KC accumulator, jt its strip-table slots.
+template <int KC, int VW, typename XT, bool HV, bool STAGED>
+__device__ __forceinline__ void process_item(
+    const ItemDesc& d, const uint8_t* __restrict__ blob, uint64_t blob_bias, const XT* __restrict__ X,
+    int64_t ldx, float* __restrict__ Y, int64_t ldy, int64_t* __restrict__ part,
+    const CombineDesc* __restrict__ combine, uint32_t* __restrict__ count, const float* __restrict__ yscale,
+    const int32_t* __restrict__ fexp, uint32_t h, uint32_t wshift, unsigned long long* acc, uint32_t* jt,
+    const float* xs, uint32_t ns, int lane) {
     constexpr bool has_val = HV;        // weighted A
     constexpr int G = KC / VW;          // lanes per X row
     constexpr int P = 64 / G;           // entries per step
     constexpr int U = KC <= 2 ? 8 : KC <= 8 ? 4 : 8;  // steps in flight per lane
-    extern __shared__ unsigned long long lds[];
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const uint32_t it = blockIdx.x * (blockDim.x >> 6) + wave;
-    if (it >= n_items) return;
-    unsigned long long* acc = lds + (size_t)wave * h * KC;
-    const ItemDesc d = items[it];
     const ItemLayout L = item_layout(d, has_val);
     const uint8_t* base = blob + (d.blob_off - blob_bias);
     const uint32_t lo = d.rows & 0xFFFFu, hi = d.rows >> 16;
@@ -179,7 +199,6 @@ __global__ __launch_bounds__(256) void spmm_items(
         const uint32_t* ent = reinterpret_cast<const uint32_t*>(base);
         const float* cval = reinterpret_cast<const float*>(base + 4 * (size_t)d.n_coo);
         const uint32_t* cJg = reinterpret_cast<const uint32_t*>(base + L.o_coo_J);
-        uint32_t* jt = reinterpret_cast<uint32_t*>(lds + (size_t)(blockDim.x >> 6) * h * KC) + wave * kJTab;
         const bool jt_lds = d.n_coo_J <= kJTab;
         if (jt_lds) {
             for (uint32_t i = lane; i < d.n_coo_J; i += 64) jt[i] = cJg[i];
@@ -222,7 +241,7 @@ __global__ __launch_bounds__(256) void spmm_items(
             float x[U][VW];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                XLd<XT, VW>::load(X + (((int64_t)J[u] << wshift) + (en[u] & 0xFFFFu)) * ldx + c0, x[u]);
+                xget<XT, KC, VW, STAGED>(X, ldx, c0, ((int64_t)J[u] << wshift) + (en[u] & 0xFFFFu), xs, ns, x[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (pb + u * P + slot <= last) {
@@ -256,7 +275,7 @@ __global__ __launch_bounds__(256) void spmm_items(
             const uint32_t start = sg.y & ((1u << kLrStartBits) - 1);
             const uint32_t lastq = start + 64u * ((sg.y >> kLrStartBits) - 1);
             const uint32_t J = lJ[sg.x >> 12];
-            const XT* xb = X + ((int64_t)J << wshift) * ldx + c0;
+            const int64_t gb = (int64_t)J << wshift;
             float s[VW];
 #pragma unroll
             for (int i = 0; i < VW; ++i) s[i] = 0.0f;
@@ -273,7 +292,7 @@ __global__ __launch_bounds__(256) void spmm_items(
                 }
                 float x[U][VW];
 #pragma unroll
-                for (int u = 0; u < U; ++u) XLd<XT, VW>::load(xb + (int64_t)cc[u] * ldx, x[u]);
+                for (int u = 0; u < U; ++u) xget<XT, KC, VW, STAGED>(X, ldx, c0, gb + cc[u], xs, ns, x[u]);
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -300,7 +319,7 @@ __global__ __launch_bounds__(256) void spmm_items(
             sg.y = __shfl(mine.y, q & 63);
             sg.z = __shfl(mine.z, q & 63);
             sg.w = __shfl(mine.w, q & 63);
-            const XT* xb = X + ((int64_t)sg.x << wshift) * ldx + c0;
+            const int64_t gb = (int64_t)sg.x << wshift;
             const uint16_t* cp = cols + sg.z;
             const float* vp = colv + sg.z;
             float s[VW];
@@ -319,7 +338,7 @@ __global__ __launch_bounds__(256) void spmm_items(
                 }
                 float x[U][VW];
 #pragma unroll
-                for (int u = 0; u < U; ++u) XLd<XT, VW>::load(xb + (int64_t)cc[u] * ldx, x[u]);
+                for (int u = 0; u < U; ++u) xget<XT, KC, VW, STAGED>(X, ldx, c0, gb + cc[u], xs, ns, x[u]);
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -369,6 +388,60 @@ __global__ __launch_bounds__(256) void spmm_items(
     if (lane == 0) atomicExch(&count[d.cid], 0u);
 }
 
+// One wavefront per work item (up to four per workgroup).
+template <int KC, int VW, typename XT, bool HV>
+__global__ __launch_bounds__(256) void spmm_items(
+    const ItemDesc* __restrict__ items, uint32_t n_items, const uint8_t* __restrict__ blob,
+    uint64_t blob_bias, const XT* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
+    int64_t* __restrict__ part, const CombineDesc* __restrict__ combine,
+    uint32_t* __restrict__ count, const float* __restrict__ yscale, const int32_t* __restrict__ fexp,
+    uint32_t h, uint32_t wshift) {
+    extern __shared__ unsigned long long lds[];
+    const uint32_t waves = blockDim.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t it = blockIdx.x * waves + wave;
+    if (it >= n_items) return;
+    unsigned long long* acc = lds + (size_t)wave * h * KC;
+    uint32_t* jt = reinterpret_cast<uint32_t*>(lds + (size_t)waves * h * KC) + wave * kJTab;
+    const ItemDesc d = items[it];
+    process_item<KC, VW, XT, HV, false>(d, blob, blob_bias, X, ldx, Y, ldy, part, combine, count, yscale, fexp, h,
+                                        wshift, acc, jt, nullptr, 0u, threadIdx.x & 63);
+}
+
+// Persistent variant with X rows staged in LDS: the workgroup first copies
+// the first ns rows of X (the hottest columns in the handle's in-degree
+// order), decoded to FP32, into LDS; then each wavefront walks the items
+// it, it + (all wavefronts), ... .  Gathers of staged rows read LDS and
+// leave the memory pipeline to the others.  Every wavefront reaches the one
+// barrier before the item loop, and every loop ends (a fixed stride over a
+// fixed count).
+template <int KC, int VW, typename XT, bool HV>
+__global__ __launch_bounds__(1024) void spmm_items_staged(
+    const ItemDesc* __restrict__ items, uint32_t n_items, const uint8_t* __restrict__ blob,
+    uint64_t blob_bias, const XT* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
+    int64_t* __restrict__ part, const CombineDesc* __restrict__ combine,
+    uint32_t* __restrict__ count, const float* __restrict__ yscale, const int32_t* __restrict__ fexp,
+    uint32_t h, uint32_t wshift, uint32_t ns) {
+    extern __shared__ unsigned long long lds[];
+    float* xs = reinterpret_cast<float*>(lds);
+    for (uint32_t t = threadIdx.x; t < ns * KC; t += blockDim.x) {
+        float v[1];
+        XLd<XT, 1>::load(X + (int64_t)(t / KC) * ldx + (t % KC), v);
+        xs[t] = v[0];
+    }
+    __syncthreads();
+    const uint32_t waves = blockDim.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unsigned long long* accs = lds + ((size_t)ns * KC + 1) / 2;  // after the staged floats, 8-byte aligned
+    unsigned long long* acc = accs + (size_t)wave * h * KC;
+    uint32_t* jt = reinterpret_cast<uint32_t*>(accs + (size_t)waves * h * KC) + wave * kJTab;
+    for (uint32_t it = blockIdx.x * waves + wave; it < n_items; it += gridDim.x * waves) {
+        const ItemDesc d = items[it];
+        process_item<KC, VW, XT, HV, true>(d, blob, blob_bias, X, ldx, Y, ldy, part, combine, count, yscale, fexp,
+                                           h, wshift, acc, jt, xs, ns, threadIdx.x & 63);
+    }
+}
+
 __global__ void colmax_init_kernel(uint32_t* m) {
     if (threadIdx.x < 64) m[threadIdx.x] = 0u;
 }
@@ -390,26 +463,79 @@ __global__ void fexp_kernel(const uint32_t* __restrict__ m, int k, double row_l1
     }
 }
 
+// Per-device launch limits, read once per device.
+struct DeviceLimits {
+    int cus = 0;
+    int max_lds = 0;
+};
+
+const DeviceLimits& device_limits() {
+    static DeviceLimits lim[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        static DeviceLimits none;
+        return none;
+    }
+    DeviceLimits& L = lim[dev];
+    if (!L.cus) {
+        int cus = 0, lds = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+            L.max_lds = lds;
+            L.cus = cus;
+        }
+    }
+    return L;
+}
+
 template <typename XT, int KC, int VW>
 hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
                       const float* yscale, const int32_t* fexp) {
+    if (!a.n_items) return hipSuccess;
+    const uint32_t per_wave = H.h * KC * 8u + kJTab * 4u;
+    // Narrow launches with staging requested: one persistent workgroup of 16
+    // wavefronts per CU with the hottest X rows staged in the LDS left over
+    // by the accumulators.
+    if constexpr (KC <= 8) {
+        const DeviceLimits& lim = device_limits();
+        constexpr uint32_t kWaves = 16;
+        const uint64_t fixed = (uint64_t)kWaves * per_wave;
+        if (H.stage_bytes && lim.cus && (uint64_t)lim.max_lds > fixed + 16384) {
+            const uint64_t budget = std::min<uint64_t>(H.stage_bytes, (uint64_t)lim.max_lds - fixed);
+            uint64_t ns = std::min<uint64_t>((uint64_t)H.n_cols, budget / (KC * 4u));
+            ns &= ~(uint64_t)1;
+            if (ns >= 1024) {
+                const size_t bytes = (size_t)ns * KC * 4u + fixed;
+                const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)lim.cus, (a.n_items + kWaves - 1) / kWaves);
+                if (H.has_val) {
+                    hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, true>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                    hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, true>), dim3(grid), dim3(64 * kWaves), bytes,
+                                       a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
+                                       H.d_part, a.combine, a.count, yscale, fexp, H.h, H.wshift, (uint32_t)ns);
+                } else {
+                    hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, false>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                    hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, false>), dim3(grid), dim3(64 * kWaves), bytes,
+                                       a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
+                                       H.d_part, a.combine, a.count, yscale, fexp, H.h, H.wshift, (uint32_t)ns);
+                }
+                return hipGetLastError();
+            }
+        }
+    }
     // 160 KB of LDS per CU; small accumulators pack four wavefronts per
     // workgroup so that the per-CU workgroup limit does not cap residency.
-    const uint32_t per_wave = H.h * KC * 8u + kJTab * 4u;
     const uint32_t wpb = per_wave <= 12288u ? 4u : per_wave <= 34816u ? 2u : 1u;
     const uint32_t grid = (a.n_items + wpb - 1) / wpb;
-    if (grid) {
-        if (H.has_val)
-            hipLaunchKernelGGL((spmm_items<KC, VW, XT, true>), dim3(grid), dim3(64 * wpb),
-                               (size_t)per_wave * wpb, a.stream, a.items, a.n_items, a.blob,
-                               a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part, a.combine, a.count,
-                               yscale, fexp, H.h, H.wshift, (int64_t)H.n_rows);
-        else
-            hipLaunchKernelGGL((spmm_items<KC, VW, XT, false>), dim3(grid), dim3(64 * wpb),
-                               (size_t)per_wave * wpb, a.stream, a.items, a.n_items, a.blob,
-                               a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part, a.combine, a.count,
-                               yscale, fexp, H.h, H.wshift, (int64_t)H.n_rows);
-    }
+    if (H.has_val)
+        hipLaunchKernelGGL((spmm_items<KC, VW, XT, true>), dim3(grid), dim3(64 * wpb), (size_t)per_wave * wpb,
+                           a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part,
+                           a.combine, a.count, yscale, fexp, H.h, H.wshift);
+    else
+        hipLaunchKernelGGL((spmm_items<KC, VW, XT, false>), dim3(grid), dim3(64 * wpb), (size_t)per_wave * wpb,
+                           a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part,
+                           a.combine, a.count, yscale, fexp, H.h, H.wshift);
     return hipGetLastError();
 }
 

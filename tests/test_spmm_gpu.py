@@ -52,7 +52,9 @@ GEOMS = [dict(tile_rows=16, tile_cols=256, item_nnz=100),      # many splits, ti
          dict(tile_rows=4096, tile_cols=1024, item_nnz=64),    # tall tile rows, tiny items
          dict(tile_rows=300, tile_cols=8192, item_nnz=5000),   # ragged tile rows
          dict(max_kc=32),
-         dict(keep_order=True, tile_rows=64)]
+         dict(keep_order=True, tile_rows=64),
+         dict(x_stage_kib=128),                                # X rows staged in LDS (k <= 8)
+         dict(x_stage_kib=4)]                                  # 1024 staged rows at k = 1 only
 
 
 @pytest.mark.parametrize("geom", GEOMS)
