@@ -25,27 +25,27 @@ spmm_status_t hip_fail(hipError_t e, const char* what) {
 bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
 void free_device(spmm::Handle& H) {
-    if (H.d_blob) hipFree(H.d_blob);
-    if (H.d_items) hipFree(H.d_items);
-    if (H.d_combine) hipFree(H.d_combine);
-    if (H.d_part) hipFree(H.d_part);
-    if (H.d_count) hipFree(H.d_count);
-    if (H.d_colmax) hipFree(H.d_colmax);
-    if (H.d_fexp) hipFree(H.d_fexp);
+    if (H.d_blob) (void)hipFree(H.d_blob);
+    if (H.d_items) (void)hipFree(H.d_items);
+    if (H.d_combine) (void)hipFree(H.d_combine);
+    if (H.d_part) (void)hipFree(H.d_part);
+    if (H.d_count) (void)hipFree(H.d_count);
+    if (H.d_colmax) (void)hipFree(H.d_colmax);
+    if (H.d_fexp) (void)hipFree(H.d_fexp);
     H.d_colmax = nullptr;
     H.d_fexp = nullptr;
-    if (H.d_col_old) hipFree(H.d_col_old);
-    if (H.d_col_count) hipFree(H.d_col_count);
+    if (H.d_col_old) (void)hipFree(H.d_col_old);
+    if (H.d_col_count) (void)hipFree(H.d_col_count);
     H.d_col_count = nullptr;
-    if (H.d_xperm) hipFree(H.d_xperm);
+    if (H.d_xperm) (void)hipFree(H.d_xperm);
     H.d_col_old = nullptr;
     H.d_xperm = nullptr;
     H.xperm_bytes = 0;
-    if (H.h_blob) hipHostFree(H.h_blob);
-    for (void* q : H.ring) hipFree(q);
-    for (hipEvent_t e : H.ev_ready) hipEventDestroy(e);
-    for (hipEvent_t e : H.ev_free) hipEventDestroy(e);
-    for (hipEvent_t e : H.timing_ev) hipEventDestroy(e);
+    if (H.h_blob) (void)hipHostFree(H.h_blob);
+    for (void* q : H.ring) (void)hipFree(q);
+    for (hipEvent_t e : H.ev_ready) (void)hipEventDestroy(e);
+    for (hipEvent_t e : H.ev_free) (void)hipEventDestroy(e);
+    for (hipEvent_t e : H.timing_ev) (void)hipEventDestroy(e);
     H.timing_ev.clear();
     H.timing_used = 0;
     H.timing = false;
@@ -138,7 +138,7 @@ spmm_status_t ensure_uploaded(spmm::Handle& H) {
 spmm_status_t ensure_partials(spmm::Handle& H) {
     const uint64_t need = H.enc.n_parts * (uint64_t)spmm::kc_cap(H);  // int64 slots
     if (need == 0 || need <= H.part_cap) return SPMM_OK;
-    if (H.d_part) hipFree(H.d_part);
+    if (H.d_part) (void)hipFree(H.d_part);
     H.d_part = nullptr;
     H.part_cap = 0;
     if (hipMalloc(&H.d_part, need * sizeof(int64_t)) != hipSuccess)
@@ -167,7 +167,7 @@ spmm_status_t prepare_device(spmm::Handle& H) {
 
 spmm_status_t ensure_xperm(spmm::Handle& H, uint64_t need) {
     if (need <= H.xperm_bytes) return SPMM_OK;
-    if (H.d_xperm) hipFree(H.d_xperm);
+    if (H.d_xperm) (void)hipFree(H.d_xperm);
     H.d_xperm = nullptr;
     H.xperm_bytes = 0;
     if (hipMalloc(&H.d_xperm, need) != hipSuccess) return fail(SPMM_ENOMEM, "hipMalloc(relabelled X) failed");
@@ -240,11 +240,12 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
         }
         ev = &H.timing_ev[H.timing_used];
         H.timing_used += 2;
-        hipEventRecord(ev[0], s);
+        hipError_t re = hipEventRecord(ev[0], s);
+        if (re != hipSuccess) return hip_fail(re, "hipEventRecord");
     }
     hipError_t e = spmm::launch_spmm(H, a);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (ev) hipEventRecord(ev[1], s);
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return SPMM_OK;
 }
 
@@ -376,9 +377,12 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
                 void* q = nullptr;
                 if (hipMalloc(&q, slot) != hipSuccess) return fail(SPMM_ENOMEM, "hipMalloc(stream ring) failed");
                 H.ring.push_back(q);
-                hipEvent_t a, b;
-                hipEventCreateWithFlags(&a, hipEventDisableTiming);
-                hipEventCreateWithFlags(&b, hipEventDisableTiming);
+                hipEvent_t a = nullptr, b = nullptr;
+                if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+                    hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+                    if (a) (void)hipEventDestroy(a);
+                    return fail(SPMM_EHIP, "hipEventCreate(stream ring) failed");
+                }
                 H.ev_ready.push_back(a);
                 H.ev_free.push_back(b);
             }
@@ -452,10 +456,25 @@ spmm_status_t spmm_pagerank(spmm_handle_t h, float damping, int iters, uint32_t 
         hipStream_t cs = nullptr;
         if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
         hipEvent_t ev = nullptr;
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        hipEventRecord(ev, s);
-        hipStreamWaitEvent(cs, ev, 0);
-        if (!(flags & SPMM_PR_INIT_GIVEN)) spmm::launch_pr_init(pr, n, (float)(1.0 / (double)n), cs);
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+            (void)hipStreamDestroy(cs);
+            return hip_fail(e, "hipEventCreate");
+        }
+        struct Cleanup {
+            hipStream_t cs;
+            hipEvent_t ev;
+            ~Cleanup() {
+                (void)hipStreamSynchronize(cs);
+                (void)hipEventDestroy(ev);
+                (void)hipStreamDestroy(cs);
+            }
+        } cleanup{cs, ev};
+        // the internal stream starts after the caller's stream's prior work
+        if ((e = hipEventRecord(ev, s)) != hipSuccess || (e = hipStreamWaitEvent(cs, ev, 0)) != hipSuccess)
+            return hip_fail(e, "stream ordering");
+        if (!(flags & SPMM_PR_INIT_GIVEN) &&
+            (e = spmm::launch_pr_init(pr, n, (float)(1.0 / (double)n), cs)) != hipSuccess)
+            return hip_fail(e, "PageRank init launch");
         const int redistribute = (flags & SPMM_PR_NO_REDISTRIBUTE) ? 0 : 1;
         // no timing events inside the captured iterations
         struct TimingOff {
@@ -493,17 +512,15 @@ spmm_status_t spmm_pagerank(spmm_handle_t h, float damping, int iters, uint32_t 
                     rs = hip_fail(e, "hipGraphInstantiate");
                 if (rs == SPMM_OK && (e = hipGraphLaunch(exec, cs)) != hipSuccess) rs = hip_fail(e, "hipGraphLaunch");
             }
-            if (rs == SPMM_OK) hipStreamSynchronize(cs);
-            if (exec) hipGraphExecDestroy(exec);
-            if (graph) hipGraphDestroy(graph);
+            if (rs == SPMM_OK) (void)hipStreamSynchronize(cs);  // checked below
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
         }
         if (rs == SPMM_OK && resid && iters > 0)
             if ((e = hipMemcpyAsync(resid, dres, sizeof(double) * (size_t)iters, hipMemcpyDeviceToHost, cs)) != hipSuccess)
                 rs = hip_fail(e, "hipMemcpy(residuals)");
         hipError_t se = hipStreamSynchronize(cs);
         if (rs == SPMM_OK && se != hipSuccess) rs = hip_fail(se, "PageRank execution");
-        hipEventDestroy(ev);
-        hipStreamDestroy(cs);
         return rs;
     } catch (const std::exception& ex) {
         return fail(SPMM_EINVAL, ex.what());

@@ -37,7 +37,7 @@ spmm_status_t launch_items_only(spmm::Handle& H, const void* X, int k, int64_t l
 struct DevBufs {
     std::vector<void*> p;
     ~DevBufs() {
-        for (void* q : p) hipFree(q);
+        for (void* q : p) (void)hipFree(q);
     }
     template <typename T>
     T* get(size_t count) {

@@ -158,19 +158,20 @@ spmm_status_t time_launches(spmm::Handle& S, const void* X, int k, int dt, const
         std::vector<hipEvent_t>& v;
         ~Guard() {
             for (auto e : v)
-                if (e) hipEventDestroy(e);
+                if (e) (void)hipEventDestroy(e);
         }
     } guard{ev};
     if ((st = launch_items_only(S, X, k, k, dt, cs, Y, k, s, fexp)) != SPMM_OK) return st;  // warm-up
-    hipEventRecord(ev[0], s);
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     for (uint32_t r = 0; r < reps; ++r) {
         if ((st = launch_items_only(S, X, k, k, dt, cs, Y, k, s, fexp)) != SPMM_OK) return st;
-        hipEventRecord(ev[r + 1], s);
+        if ((e = hipEventRecord(ev[r + 1], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    hipError_t e = hipEventSynchronize(ev[reps]);
-    if (e != hipSuccess) return hip_fail(e, "bucket timing");
+    if ((e = hipEventSynchronize(ev[reps])) != hipSuccess) return hip_fail(e, "bucket timing");
     std::vector<float> t(reps);
-    for (uint32_t r = 0; r < reps; ++r) hipEventElapsedTime(&t[r], ev[r], ev[r + 1]);
+    for (uint32_t r = 0; r < reps; ++r)
+        if ((e = hipEventElapsedTime(&t[r], ev[r], ev[r + 1])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
     ms = t[reps / 2];
     return SPMM_OK;
@@ -407,8 +408,8 @@ spmm_status_t spmm_selector_train(const float* feat, const float* target, const 
         struct StreamGuard {
             hipStream_t s;
             ~StreamGuard() {
-                hipStreamSynchronize(s);
-                hipStreamDestroy(s);
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
             }
         } sg{s};
         if ((e = hipMemcpyAsync(dfeat, feat, (size_t)n * F * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||

@@ -508,13 +508,15 @@ hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
                 const size_t bytes = (size_t)ns * KC * 4u + fixed;
                 const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)lim.cus, (a.n_items + kWaves - 1) / kWaves);
                 if (H.has_val) {
-                    hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, true>),
+                    // raises the dynamic-LDS limit where the runtime asks for it; a
+                    // launch beyond the device's limit fails and is reported below
+                    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, true>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, true>), dim3(grid), dim3(64 * kWaves), bytes,
                                        a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
                                        H.d_part, a.combine, a.count, yscale, fexp, H.h, H.wshift, (uint32_t)ns);
                 } else {
-                    hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, false>),
+                    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, false>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, false>), dim3(grid), dim3(64 * kWaves), bytes,
                                        a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
