@@ -94,7 +94,9 @@ typedef struct {
                                  longer rows are split; 0 -> 16384, <= 131072      */
     uint32_t place;          /* spmm_place_t                                     */
     uint32_t threads;        /* host threads for the build; 0 -> all cores       */
-    uint32_t validate;       /* 1 -> reject unsorted/duplicate/out-of-range CSR  */
+    uint32_t validate;       /* row pointers and column ranges are always
+                                 checked; 1 also rejects unsorted or duplicate
+                                 columns within a row (duplicates otherwise add) */
     uint32_t max_kc;         /* widest block of X columns one kernel launch
                                  accumulates: 16 or 32; 0 -> 32                   */
     uint32_t keep_order;     /* 0 (default): tiles index columns by descending

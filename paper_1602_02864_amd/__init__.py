@@ -238,18 +238,35 @@ def spmm_destroy(h: Handle):
 def _xdtype(X, dtype):
     if dtype is not None:
         return dtype
-    name = str(getattr(X, "dtype", "float32"))
-    if "bfloat16" in name:
-        return SPMM_X_BF16
-    if "uint8" in name or "float8" in name:
-        return SPMM_X_FP8_E4M3
-    return SPMM_X_F32
+    return _X_TORCH_DTYPES.get(str(getattr(X, "dtype", "torch.float32")), SPMM_X_F32)
+
+
+# X tensor types: FP32 values, BF16 values or raw 16-bit codes, E4M3 raw 8-bit codes
+_X_TORCH_DTYPES = {"torch.float32": SPMM_X_F32, "torch.bfloat16": SPMM_X_BF16, "torch.uint16": SPMM_X_BF16,
+                   "torch.int16": SPMM_X_BF16, "torch.uint8": SPMM_X_FP8_E4M3, "torch.int8": SPMM_X_FP8_E4M3,
+                   "torch.float8_e4m3fn": SPMM_X_FP8_E4M3}
+
+
+def _check_tensors(X, Y, dtype):
+    """Shape/type checks for torch tensors (raw pointers pass through)."""
+    if hasattr(X, "data_ptr") and hasattr(X, "dtype"):
+        name = str(X.dtype)
+        if name not in _X_TORCH_DTYPES:
+            raise TypeError(f"X must be float32, bfloat16 (or 16-bit codes) or 8-bit E4M3 codes, not {name}")
+        if dtype is not None and _X_TORCH_DTYPES[name] != dtype:
+            raise TypeError(f"X dtype {name} does not match dtype={dtype}")
+        if X.dim() != 2 or X.stride(1) != 1 or not X.is_cuda:
+            raise ValueError("X must be a 2-D device tensor with unit column stride")
+    if hasattr(Y, "data_ptr") and hasattr(Y, "dtype"):
+        if str(Y.dtype) != "torch.float32" or Y.dim() != 2 or Y.stride(1) != 1 or not Y.is_cuda:
+            raise ValueError("Y must be a 2-D float32 device tensor with unit column stride")
 
 
 def spmm_run(h: Handle, X, Y, k: int | None = None, ldx: int | None = None, dtype: int | None = None,
              col_scale=None, ldy: int | None = None, stream=None):
     """Y = A X on the device.  X, Y: 2-D row-major device tensors (or pointers
     with k/ldx/ldy given); X's dtype selects F32/BF16/FP8 unless ``dtype``."""
+    _check_tensors(X, Y, dtype)
     L = load_library()
     if k is None:
         k = X.shape[1]
@@ -282,6 +299,7 @@ def spmm_quantize_x(X, Xq, dtype: int, col_scale=None, flags: int = 0, n: int | 
 def spmm_stream_run(h: Handle, X, Y, compute=None, copy=None, k: int | None = None, ldx: int | None = None,
                     dtype: int | None = None, col_scale=None, ldy: int | None = None):
     """Y = A X with A streamed from pinned host memory (see spmm.h)."""
+    _check_tensors(X, Y, dtype)
     L = load_library()
     k = X.shape[1] if k is None else k
     ldx = X.stride(0) if ldx is None else ldx
