@@ -193,13 +193,37 @@ spmm_status_t spmm_quantize_x(const float* X, int64_t n, int k, int64_t ldx, spm
  *   h : built with opts.place = SPMM_PLACE_PINNED_HOST.  Other arguments as
  *       spmm_run.  compute and copy should be different streams for overlap.
  * The result is identical to spmm_run's on the same tiles (same kernels,
- * same work items).  Asynchronous.  The first call allocates the ring.
+ * same work items).  Asynchronous, except that a call first waits on the
+ * host until the previous call's kernels have finished with the ring.  The
+ * first call allocates the ring.
  * Errors: SPMM_EINVAL, SPMM_ESTATE (tiles placed in HBM), SPMM_ENOMEM,
  * SPMM_EHIP.
  */
 spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
                               const float* col_scale, float* Y, int64_t ldy, hipStream_t compute,
                               hipStream_t copy);
+
+/*
+ * Semi-external SpMM with the dense matrices in host memory as well: X and
+ * Y stay in (pinned) host DRAM and their columns are processed in blocks of
+ * cols_per_block -- the paper's dense matrix partly in memory (Section 3.5's
+ * memory and I/O model, Section 3.6).  For each block the library copies
+ * that block of X to the device, streams all of A over it (as
+ * spmm_stream_run), and copies the block of Y back while the next block
+ * starts.  A crosses the host link ceil(k / cols_per_block) times, so fewer
+ * columns in memory cost more A traffic: the trade-off the paper measures.
+ *   h : built with opts.place = SPMM_PLACE_PINNED_HOST.
+ *   X : host FP32 [n_cols][ldx], ldx >= k (pinned memory for full speed).
+ *   Y : host FP32 [n_rows][ldy], ldy >= k, fully overwritten.
+ *   cols_per_block : 1..k.
+ * Device memory for two X blocks and two Y blocks (n x cols_per_block FP32)
+ * is allocated per call.  Synchronous: returns when Y is in host memory.
+ * The result is identical to spmm_run's on the same tiles.
+ * Errors: SPMM_EINVAL, SPMM_ESTATE (tiles placed in HBM), SPMM_ENOMEM,
+ * SPMM_EHIP.
+ */
+spmm_status_t spmm_stream_run_host(spmm_handle_t h, const float* X, int k, int64_t ldx, float* Y, int64_t ldy,
+                                   int cols_per_block);
 
 /*
  * PageRank power iteration (Section 4.1):

@@ -134,6 +134,7 @@ def load_library():
             ("spmm_selector_train", [vp, vp, vp, i64, ctypes.POINTER(spmm_train_opts), vp, vp]),
             ("spmm_select_learned", [vp, vp, i32, i32]),
             ("spmm_timing_begin", [vp]),
+            ("spmm_stream_run_host", [vp, vp, i32, i64, vp, i64, i32]),
             ("spmm_read_probe", [vp, ctypes.c_uint64, vp, vp]),
             ("spmm_timing_end", [vp, vp, vp])]:
         fn = getattr(L, name)
@@ -307,6 +308,21 @@ def spmm_stream_run(h: Handle, X, Y, compute=None, copy=None, k: int | None = No
     st = L.spmm_stream_run(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
                            int(ldy), _stream(compute, X), _stream(copy))
     _check(st, "spmm_stream_run")
+
+
+def spmm_stream_run_host(h: Handle, X, Y, cols_per_block: int, k: int | None = None,
+                         ldx: int | None = None, ldy: int | None = None):
+    """Y = A X with A, X and Y in (pinned) host memory, X/Y columns in blocks."""
+    for name, T in (("X", X), ("Y", Y)):
+        if hasattr(T, "dtype") and (str(T.dtype) not in ("torch.float32", "float32") or
+                                    getattr(T, "is_cuda", False) or T.ndim != 2):
+            raise ValueError(f"{name} must be a 2-D float32 host array")
+    k = X.shape[1] if k is None else k
+    ldx = (X.stride(0) if hasattr(X, "stride") and callable(X.stride) else X.strides[0] // 4) if ldx is None else ldx
+    ldy = (Y.stride(0) if hasattr(Y, "stride") and callable(Y.stride) else Y.strides[0] // 4) if ldy is None else ldy
+    st = load_library().spmm_stream_run_host(h.ptr, _ptr(X), int(k), int(ldx), _ptr(Y), int(ldy),
+                                             int(cols_per_block))
+    _check(st, "spmm_stream_run_host")
 
 
 SPMM_PR_INIT_GIVEN, SPMM_PR_NO_REDISTRIBUTE, SPMM_PR_NO_GRAPH = 1, 2, 4

@@ -50,6 +50,7 @@ void free_device(spmm::Handle& H) {
     H.timing_used = 0;
     H.timing = false;
     H.ring.clear();
+    H.ring_used.clear();
     H.ev_ready.clear();
     H.ev_free.clear();
     H.d_blob = H.h_blob = nullptr;
@@ -385,7 +386,16 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
                 }
                 H.ev_ready.push_back(a);
                 H.ev_free.push_back(b);
+                H.ring_used.push_back(0);
             }
+        }
+        // Calls do not overlap: before this call copies into the ring, the
+        // host waits until the kernels of the previous call have finished
+        // reading it (the copies within one call are ordered by events).
+        for (size_t r = 0; r < H.ring.size(); ++r) {
+            if (!H.ring_used[r]) continue;
+            hipError_t e = hipEventSynchronize(H.ev_free[r]);
+            if (e != hipSuccess) return hip_fail(e, "previous streamed call");
         }
         spmm::RunArgs a{};
         if ((st = prepare_x(H, X, k, ldx, dt, compute, false, a)) != SPMM_OK) return st;
@@ -404,7 +414,10 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
             hipError_t e;
             // the copy into a slot waits until the kernels reading its
             // previous group are done; the kernels wait for their copy
-            if (g >= R && (e = hipStreamWaitEvent(copy, H.ev_free[slot], 0)) != hipSuccess) return hip_fail(e, "wait");
+            // also across calls: the previous call's last kernels may still
+            // be reading the slot this call's first copies fill
+            if (H.ring_used[slot] && (e = hipStreamWaitEvent(copy, H.ev_free[slot], 0)) != hipSuccess)
+                return hip_fail(e, "wait");
             if ((e = hipMemcpyAsync(H.ring[slot], static_cast<uint8_t*>(H.h_blob) + G.b0, G.b1 - G.b0,
                                     hipMemcpyHostToDevice, copy)) != hipSuccess)
                 return hip_fail(e, "hipMemcpyAsync(tile group)");
@@ -416,7 +429,79 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
             a.n_items = (uint32_t)(G.i1 - G.i0);
             if ((e = spmm::launch_spmm(H, a)) != hipSuccess) return hip_fail(e, "kernel launch");
             if ((e = hipEventRecord(H.ev_free[slot], compute)) != hipSuccess) return hip_fail(e, "record");
+            H.ring_used[slot] = 1;
         }
+        return SPMM_OK;
+    } catch (const std::exception& ex) {
+        return fail(SPMM_EINVAL, ex.what());
+    }
+}
+
+spmm_status_t spmm_stream_run_host(spmm_handle_t h, const float* X, int k, int64_t ldx, float* Y, int64_t ldy,
+                                   int cols_per_block) {
+    try {
+        if (!h) return fail(SPMM_EINVAL, "handle is NULL");
+        spmm::Handle& H = h->H;
+        if (H.place != SPMM_PLACE_PINNED_HOST)
+            return fail(SPMM_ESTATE, "tiles are placed in HBM; build with place = SPMM_PLACE_PINNED_HOST");
+        if (k < 1 || k > 64) return fail(SPMM_EINVAL, "k must be in 1..64");
+        if (cols_per_block < 1 || cols_per_block > k) return fail(SPMM_EINVAL, "cols_per_block must be in 1..k");
+        if (ldx < k || ldy < k) return fail(SPMM_EINVAL, "ldx and ldy must be >= k");
+        if ((H.n_cols > 0 && !X) || (H.n_rows > 0 && !Y)) return fail(SPMM_EINVAL, "X or Y is NULL");
+        if (H.n_rows == 0) return SPMM_OK;
+        const int cb = cols_per_block;
+        const size_t xrows = (size_t)std::max<int64_t>(H.n_cols, 1), yrows = (size_t)H.n_rows;
+        DevBufs B;
+        float* xb[2] = {B.get<float>(xrows * cb), B.get<float>(xrows * cb)};
+        float* yb[2] = {B.get<float>(yrows * cb), B.get<float>(yrows * cb)};
+        if (!xb[0] || !xb[1] || !yb[0] || !yb[1]) return fail(SPMM_ENOMEM, "hipMalloc(column blocks) failed");
+        hipStream_t st[3] = {nullptr, nullptr, nullptr};  // compute, host -> device, device -> host
+        hipEvent_t ev[7] = {};  // x ready, x free (2), y ready, y free (2), spare
+        struct Guard {
+            hipStream_t* st;
+            hipEvent_t* ev;
+            ~Guard() {
+                for (int i = 0; i < 3; ++i)
+                    if (st[i]) (void)hipStreamSynchronize(st[i]);
+                for (int i = 0; i < 7; ++i)
+                    if (ev[i]) (void)hipEventDestroy(ev[i]);
+                for (int i = 0; i < 3; ++i)
+                    if (st[i]) (void)hipStreamDestroy(st[i]);
+            }
+        } guard{st, ev};
+        hipError_t e;
+        for (int i = 0; i < 3; ++i)
+            if ((e = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreate");
+        for (int i = 0; i < 7; ++i)
+            if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreate");
+        hipEvent_t x_ready = ev[0], x_free[2] = {ev[1], ev[2]}, y_ready = ev[3], y_free[2] = {ev[4], ev[5]};
+        const int nblk = (k + cb - 1) / cb;
+        for (int b = 0; b < nblk; ++b) {
+            const int c0 = b * cb, w = std::min(cb, k - c0), slot = b & 1;
+            // X block b -> device, once the kernels of block b - 2 have read the slot
+            if (b >= 2 && (e = hipStreamWaitEvent(st[1], x_free[slot], 0)) != hipSuccess) return hip_fail(e, "wait");
+            if (H.n_cols > 0 &&
+                (e = hipMemcpy2DAsync(xb[slot], (size_t)w * 4, X + c0, (size_t)ldx * 4, (size_t)w * 4, (size_t)H.n_cols,
+                                      hipMemcpyHostToDevice, st[1])) != hipSuccess)
+                return hip_fail(e, "hipMemcpy2DAsync(X block)");
+            if ((e = hipEventRecord(x_ready, st[1])) != hipSuccess || (e = hipStreamWaitEvent(st[0], x_ready, 0)) != hipSuccess)
+                return hip_fail(e, "X block ordering");
+            // the Y slot is free once block b - 2 has been copied back
+            if (b >= 2 && (e = hipStreamWaitEvent(st[0], y_free[slot], 0)) != hipSuccess) return hip_fail(e, "wait");
+            spmm_status_t rs = spmm_stream_run(h, xb[slot], w, w, SPMM_X_F32, nullptr, yb[slot], w, st[0], st[1]);
+            if (rs != SPMM_OK) return rs;
+            if ((e = hipEventRecord(x_free[slot], st[0])) != hipSuccess || (e = hipEventRecord(y_ready, st[0])) != hipSuccess ||
+                (e = hipStreamWaitEvent(st[2], y_ready, 0)) != hipSuccess)
+                return hip_fail(e, "Y block ordering");
+            if ((e = hipMemcpy2DAsync(Y + c0, (size_t)ldy * 4, yb[slot], (size_t)w * 4, (size_t)w * 4, yrows,
+                                      hipMemcpyDeviceToHost, st[2])) != hipSuccess)
+                return hip_fail(e, "hipMemcpy2DAsync(Y block)");
+            if ((e = hipEventRecord(y_free[slot], st[2])) != hipSuccess) return hip_fail(e, "record");
+        }
+        for (int i = 0; i < 3; ++i)
+            if ((e = hipStreamSynchronize(st[i])) != hipSuccess) return hip_fail(e, "column-block SpMM");
         return SPMM_OK;
     } catch (const std::exception& ex) {
         return fail(SPMM_EINVAL, ex.what());

@@ -151,6 +151,7 @@ struct Handle {
     uint32_t ring_depth = 0;
     std::vector<void*> ring;      // device slots, each max group bytes
     std::vector<hipEvent_t> ev_ready, ev_free;
+    std::vector<uint8_t> ring_used;  // slot has been read by a kernel (ev_free recorded)
     int device = 0;
     bool uploaded = false;
     // optional timing of the SpMM launches of each run (event pairs)
