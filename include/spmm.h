@@ -213,17 +213,29 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
  * starts.  A crosses the host link ceil(k / cols_per_block) times, so fewer
  * columns in memory cost more A traffic: the trade-off the paper measures.
  *   h : built with opts.place = SPMM_PLACE_PINNED_HOST.
- *   X : host FP32 [n_cols][ldx], ldx >= k (pinned memory for full speed).
- *   Y : host FP32 [n_rows][ldy], ldy >= k, fully overwritten.
+ *   X : host FP32, pinned memory for full speed.  Row-major [n_cols][ldx]
+ *       (ldx >= k), or with SPMM_HOSTXY_BLOCKED the blocked layout: block b
+ *       (columns b*cols_per_block ... up to k) stored contiguously as
+ *       [n_cols][width of block b], blocks back to back (ldx ignored).
+ *   Y : host FP32 [n_rows][ldy] (ldy >= k), or blocked like X; fully
+ *       overwritten.
  *   cols_per_block : 1..k.
+ * A block that is contiguous in host memory (blocked layout, or
+ * cols_per_block = k = ldx) crosses the link as one copy; strided columns
+ * of a row-major X or Y need a 2-D copy, which the copy engines perform far
+ * below the link rate for narrow rows.
  * Device memory for two X blocks and two Y blocks (n x cols_per_block FP32)
  * is allocated per call.  Synchronous: returns when Y is in host memory.
- * The result is identical to spmm_run's on the same tiles.
+ * The result equals spmm_run's on the same tiles up to the FP32 rounding of
+ * per-row register partial sums, whose lane order depends on the column
+ * width of a launch (bit-identical when cols_per_block equals the launch
+ * width spmm_run uses, and for integer-valued X).
  * Errors: SPMM_EINVAL, SPMM_ESTATE (tiles placed in HBM), SPMM_ENOMEM,
  * SPMM_EHIP.
  */
+#define SPMM_HOSTXY_BLOCKED 1u
 spmm_status_t spmm_stream_run_host(spmm_handle_t h, const float* X, int k, int64_t ldx, float* Y, int64_t ldy,
-                                   int cols_per_block);
+                                   int cols_per_block, uint32_t flags);
 
 /*
  * PageRank power iteration (Section 4.1):

@@ -134,7 +134,7 @@ def load_library():
             ("spmm_selector_train", [vp, vp, vp, i64, ctypes.POINTER(spmm_train_opts), vp, vp]),
             ("spmm_select_learned", [vp, vp, i32, i32]),
             ("spmm_timing_begin", [vp]),
-            ("spmm_stream_run_host", [vp, vp, i32, i64, vp, i64, i32]),
+            ("spmm_stream_run_host", [vp, vp, i32, i64, vp, i64, i32, ctypes.c_uint32]),
             ("spmm_read_probe", [vp, ctypes.c_uint64, vp, vp]),
             ("spmm_timing_end", [vp, vp, vp])]:
         fn = getattr(L, name)
@@ -310,18 +310,32 @@ def spmm_stream_run(h: Handle, X, Y, compute=None, copy=None, k: int | None = No
     _check(st, "spmm_stream_run")
 
 
+SPMM_HOSTXY_BLOCKED = 1
+
+
 def spmm_stream_run_host(h: Handle, X, Y, cols_per_block: int, k: int | None = None,
-                         ldx: int | None = None, ldy: int | None = None):
-    """Y = A X with A, X and Y in (pinned) host memory, X/Y columns in blocks."""
+                         ldx: int | None = None, ldy: int | None = None, blocked: bool = False):
+    """Y = A X with A, X and Y in (pinned) host memory, X/Y columns in blocks.
+
+    Row-major 2-D X and Y by default; with ``blocked`` X and Y are 1-D host
+    arrays holding the column blocks back to back (k must be given)."""
     for name, T in (("X", X), ("Y", Y)):
         if hasattr(T, "dtype") and (str(T.dtype) not in ("torch.float32", "float32") or
-                                    getattr(T, "is_cuda", False) or T.ndim != 2):
-            raise ValueError(f"{name} must be a 2-D float32 host array")
-    k = X.shape[1] if k is None else k
-    ldx = (X.stride(0) if hasattr(X, "stride") and callable(X.stride) else X.strides[0] // 4) if ldx is None else ldx
-    ldy = (Y.stride(0) if hasattr(Y, "stride") and callable(Y.stride) else Y.strides[0] // 4) if ldy is None else ldy
+                                    getattr(T, "is_cuda", False) or (T.ndim != 2 and not blocked)):
+            raise ValueError(f"{name} must be a float32 host array (2-D unless blocked)")
+
+    def lead(T):
+        return T.stride(0) if hasattr(T, "stride") and callable(T.stride) else T.strides[0] // 4
+    if blocked:
+        if k is None:
+            raise ValueError("blocked layout needs k")
+        ldx = ldy = 0
+    else:
+        k = X.shape[1] if k is None else k
+        ldx = lead(X) if ldx is None else ldx
+        ldy = lead(Y) if ldy is None else ldy
     st = load_library().spmm_stream_run_host(h.ptr, _ptr(X), int(k), int(ldx), _ptr(Y), int(ldy),
-                                             int(cols_per_block))
+                                             int(cols_per_block), SPMM_HOSTXY_BLOCKED if blocked else 0)
     _check(st, "spmm_stream_run_host")
 
 

@@ -438,7 +438,7 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
 }
 
 spmm_status_t spmm_stream_run_host(spmm_handle_t h, const float* X, int k, int64_t ldx, float* Y, int64_t ldy,
-                                   int cols_per_block) {
+                                   int cols_per_block, uint32_t flags) {
     try {
         if (!h) return fail(SPMM_EINVAL, "handle is NULL");
         spmm::Handle& H = h->H;
@@ -446,7 +446,9 @@ spmm_status_t spmm_stream_run_host(spmm_handle_t h, const float* X, int k, int64
             return fail(SPMM_ESTATE, "tiles are placed in HBM; build with place = SPMM_PLACE_PINNED_HOST");
         if (k < 1 || k > 64) return fail(SPMM_EINVAL, "k must be in 1..64");
         if (cols_per_block < 1 || cols_per_block > k) return fail(SPMM_EINVAL, "cols_per_block must be in 1..k");
-        if (ldx < k || ldy < k) return fail(SPMM_EINVAL, "ldx and ldy must be >= k");
+        if (flags & ~SPMM_HOSTXY_BLOCKED) return fail(SPMM_EINVAL, "unknown flags");
+        const bool blocked = (flags & SPMM_HOSTXY_BLOCKED) != 0;
+        if (!blocked && (ldx < k || ldy < k)) return fail(SPMM_EINVAL, "ldx and ldy must be >= k");
         if ((H.n_cols > 0 && !X) || (H.n_rows > 0 && !Y)) return fail(SPMM_EINVAL, "X or Y is NULL");
         if (H.n_rows == 0) return SPMM_OK;
         const int cb = cols_per_block;
@@ -482,10 +484,16 @@ spmm_status_t spmm_stream_run_host(spmm_handle_t h, const float* X, int k, int64
             const int c0 = b * cb, w = std::min(cb, k - c0), slot = b & 1;
             // X block b -> device, once the kernels of block b - 2 have read the slot
             if (b >= 2 && (e = hipStreamWaitEvent(st[1], x_free[slot], 0)) != hipSuccess) return hip_fail(e, "wait");
-            if (H.n_cols > 0 &&
-                (e = hipMemcpy2DAsync(xb[slot], (size_t)w * 4, X + c0, (size_t)ldx * 4, (size_t)w * 4, (size_t)H.n_cols,
-                                      hipMemcpyHostToDevice, st[1])) != hipSuccess)
-                return hip_fail(e, "hipMemcpy2DAsync(X block)");
+            if (H.n_cols > 0) {
+                // block b's X in host memory: contiguous (blocked layout, or a
+                // full-width row-major X) or w columns of ldx-strided rows
+                const float* xs = blocked ? X + (size_t)c0 * H.n_cols : X + c0;
+                const bool contiguous = blocked || (size_t)w == (size_t)ldx;
+                e = contiguous ? hipMemcpyAsync(xb[slot], xs, (size_t)w * 4 * H.n_cols, hipMemcpyHostToDevice, st[1])
+                               : hipMemcpy2DAsync(xb[slot], (size_t)w * 4, xs, (size_t)ldx * 4, (size_t)w * 4,
+                                                  (size_t)H.n_cols, hipMemcpyHostToDevice, st[1]);
+                if (e != hipSuccess) return hip_fail(e, "copy of an X block");
+            }
             if ((e = hipEventRecord(x_ready, st[1])) != hipSuccess || (e = hipStreamWaitEvent(st[0], x_ready, 0)) != hipSuccess)
                 return hip_fail(e, "X block ordering");
             // the Y slot is free once block b - 2 has been copied back
@@ -495,9 +503,14 @@ spmm_status_t spmm_stream_run_host(spmm_handle_t h, const float* X, int k, int64
             if ((e = hipEventRecord(x_free[slot], st[0])) != hipSuccess || (e = hipEventRecord(y_ready, st[0])) != hipSuccess ||
                 (e = hipStreamWaitEvent(st[2], y_ready, 0)) != hipSuccess)
                 return hip_fail(e, "Y block ordering");
-            if ((e = hipMemcpy2DAsync(Y + c0, (size_t)ldy * 4, yb[slot], (size_t)w * 4, (size_t)w * 4, yrows,
-                                      hipMemcpyDeviceToHost, st[2])) != hipSuccess)
-                return hip_fail(e, "hipMemcpy2DAsync(Y block)");
+            {
+                float* ys = blocked ? Y + (size_t)c0 * yrows : Y + c0;
+                const bool contiguous = blocked || (size_t)w == (size_t)ldy;
+                e = contiguous ? hipMemcpyAsync(ys, yb[slot], (size_t)w * 4 * yrows, hipMemcpyDeviceToHost, st[2])
+                               : hipMemcpy2DAsync(ys, (size_t)ldy * 4, yb[slot], (size_t)w * 4, (size_t)w * 4, yrows,
+                                                  hipMemcpyDeviceToHost, st[2]);
+                if (e != hipSuccess) return hip_fail(e, "copy of a Y block");
+            }
             if ((e = hipEventRecord(y_free[slot], st[2])) != hipSuccess) return hip_fail(e, "record");
         }
         for (int i = 0; i < 3; ++i)

@@ -86,6 +86,15 @@ def test_host_resident_column_blocks_equal_in_hbm(weighted):
         pk.spmm_stream_run_host(hs, Xh, Yh[:, :k], cb)
         assert torch.equal(Yh[:, :k], ref), cb
         assert torch.isnan(Yh[:, k:]).all()      # columns beyond k untouched
+        # blocked layout: each block of columns contiguous, blocks back to back
+        blocks = [(c0, min(cb, k - c0)) for c0 in range(0, k, cb)]
+        Xb = torch.cat([Xh[:, c0:c0 + w].reshape(-1) for c0, w in blocks]).pin_memory()
+        Yb = torch.full((n * k,), float("nan")).pin_memory()
+        pk.spmm_stream_run_host(hs, Xb, Yb, cb, k=k, blocked=True)
+        off = 0
+        for c0, w in blocks:
+            assert torch.equal(Yb[off:off + n * w].reshape(n, w), ref[:, c0:c0 + w]), (cb, c0)
+            off += n * w
     with pytest.raises(pk.SpmmError) as ei:
         pk.spmm_stream_run_host(hd, Xh, Yh[:, :k], 2)
     assert ei.value.status == pk.SPMM_ESTATE
