@@ -156,7 +156,8 @@ def main() -> int:
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="run a plain device copy of this many GiB first (counter calibration)")
     ap.add_argument("--mode", default="spmm",
-                    help="spmm (default) | stream | colblocks | precision | apps (comma-separated)")
+                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps "
+                         "(comma-separated)")
     ap.add_argument("--stream-kib", type=int, default=0, help="streamed mode: bytes per transfer group")
     ap.add_argument("--ring-depth", type=int, default=0, help="streamed mode: device ring slots")
     args = ap.parse_args()
@@ -599,6 +600,46 @@ def run_other_modes(args, modes) -> int:
             hd.close()
             hs.close()
             del Xd, Yd, ref
+        elif mode == "apps_directed":
+            # the directed graph: PageRank on the in-link matrix A^T and NMF
+            # with A and A^T, both transposed by the library's build
+            if sym:
+                raise SystemExit("apps_directed needs the directed graph (run it without precision/apps)")
+            t0 = time.perf_counter()
+            hT = pk.spmm_build_tiles(rp, col, validate=False, transpose=True)
+            t_tb = time.perf_counter() - t0
+            hA = pk.spmm_build_tiles(rp, col, validate=False)
+            log(f"transposed build {t_tb:.1f}s")
+            pr = torch.empty(n, device=dev)
+            pk.spmm_pagerank(hT, pr, iters=2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            resid = pk.spmm_pagerank(hT, pr, iters=30)
+            t_pr = time.perf_counter() - t0
+            s_pr = float(pr.double().sum().item())
+            W = torch.from_numpy(synth.uniform(n, 16, seed=synth.SEED_W)).to(dev)
+            Hm = torch.from_numpy(synth.uniform(n, 16, seed=synth.SEED_H)).to(dev)
+            pk.spmm_nmf(hA, hT, W, Hm, iters=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pk.spmm_nmf(hA, hT, W, Hm, iters=10)
+            torch.cuda.synchronize()
+            t_nmf = time.perf_counter() - t0
+            ok_nmf = bool(torch.isfinite(W).all().item() and torch.isfinite(Hm).all().item()
+                          and (W >= 0).all().item() and (Hm >= 0).all().item())
+            out = {"mode": "apps_directed", "metric": "PageRank and NMF time per iteration (directed graph)",
+                   "n_gpus": 1, "data": "synthetic", "config": {"workload": workload, "n": n, "nnz": nnz},
+                   "transposed_build_s": round(t_tb, 1),
+                   "pagerank_ms_per_iter": round(t_pr * 1e3 / 30, 3), "pagerank_sum": s_pr,
+                   "pagerank_resid_first_last": [float(resid[0]), float(resid[-1])],
+                   "nmf_ms_per_iter": round(t_nmf * 1e3 / 10, 3),
+                   "nmf_spmm_gflops": round(2 * 2.0 * nnz * 16 / (t_nmf / 10) / 1e9, 2),
+                   "nmf_factors_finite_nonneg": ok_nmf}
+            log(f"apps_directed: {out}")
+            print(json.dumps(out), flush=True)
+            del W, Hm, pr
+            hT.close()
+            hA.close()
         elif mode == "precision":
             vals = synth.lognormal_weights(rp, col, seed=synth.SEED_WEIGHT)
             log("weights drawn")

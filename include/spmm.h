@@ -113,6 +113,10 @@ typedef struct {
                                  workgroup (a persistent launch, one workgroup
                                  per CU; capped by the device's LDS); <= 0 -> no
                                  staging (the default: measured faster)          */
+    uint32_t transpose;      /* 1 -> the handle holds A^T: the given CSR is
+                                 transposed on the host first (for PageRank's
+                                 in-link matrix and NMF's A^T on a directed
+                                 graph); its shape is then n_cols x n_rows       */
 } spmm_build_opts;
 
 typedef struct spmm_handle_s* spmm_handle_t;

@@ -307,6 +307,21 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         if (o.fixed_variant >= SPMM_NUM_VARIANTS) return fail(SPMM_EINVAL, "unknown variant");
         if (o.place != SPMM_PLACE_DEVICE && o.place != SPMM_PLACE_PINNED_HOST)
             return fail(SPMM_EINVAL, "unknown placement");
+        if (o.transpose > 1) return fail(SPMM_EINVAL, "transpose must be 0 or 1");
+        // with transpose, tile the CSR of A^T instead (rows and columns swap)
+        std::vector<int64_t> t_ptr;
+        std::vector<int32_t> t_col;
+        std::vector<float> t_val;
+        if (o.transpose) {
+            std::string terr;
+            spmm_status_t ts = spmm::transpose_csr(n_rows, n_cols, row_ptr, col_idx, values, o.threads, t_ptr,
+                                                   t_col, t_val, terr);
+            if (ts != SPMM_OK) return fail(ts, terr);
+            std::swap(n_rows, n_cols);
+            row_ptr = t_ptr.data();
+            col_idx = t_col.empty() ? nullptr : t_col.data();
+            values = values ? t_val.data() : nullptr;
+        }
         std::unique_ptr<spmm_handle_s> hs(new spmm_handle_s);
         spmm::Handle& H = hs->H;
         H.n_rows = n_rows;

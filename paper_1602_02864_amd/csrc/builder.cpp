@@ -46,6 +46,66 @@ static uint32_t log2_exact(uint32_t x) {
     return s;
 }
 
+spmm_status_t transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr, const int32_t* col,
+                            const float* val, uint32_t threads, std::vector<int64_t>& tp, std::vector<int32_t>& tc,
+                            std::vector<float>& tv, std::string& err) {
+    if (row_ptr[0] != 0) {
+        err = "row_ptr[0] must be 0";
+        return SPMM_EINVAL;
+    }
+    const int64_t nnz = row_ptr[n_rows];
+    // the same range checks as the tile build, before any index is used
+    std::atomic<int> bad{0};
+    parallel_for((uint64_t)n_rows, threads, 1 << 16, [&](uint64_t a, uint64_t b) {
+        for (uint64_t i = a; i < b && !bad; ++i) {
+            if (row_ptr[i + 1] < row_ptr[i]) { bad = 1; return; }
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+                if (col[p] < 0 || col[p] >= n_cols) { bad = 2; return; }
+        }
+    });
+    if (bad) {
+        err = bad == 1 ? "row_ptr is not non-decreasing" : "column index out of range";
+        return SPMM_EINVAL;
+    }
+    tp.assign((size_t)n_cols + 1, 0);
+    tc.resize((size_t)nnz);
+    if (val) tv.resize((size_t)nnz);
+    // counts per column, then positions by prefix sum
+    parallel_for((uint64_t)n_rows, threads, 1 << 14, [&](uint64_t a, uint64_t b) {
+        for (int64_t p = row_ptr[a]; p < row_ptr[b]; ++p) __atomic_fetch_add(&tp[(size_t)col[p] + 1], 1, __ATOMIC_RELAXED);
+    });
+    for (int64_t c = 0; c < n_cols; ++c) tp[(size_t)c + 1] += tp[(size_t)c];
+    std::vector<int64_t> cursor(tp.begin(), tp.end() - 1);
+    parallel_for((uint64_t)n_rows, threads, 1 << 14, [&](uint64_t a, uint64_t b) {
+        for (uint64_t i = a; i < b; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                const int64_t q = __atomic_fetch_add(&cursor[(size_t)col[p]], 1, __ATOMIC_RELAXED);
+                tc[(size_t)q] = (int32_t)i;
+                if (val) tv[(size_t)q] = val[p];
+            }
+    });
+    // the scatter order depends on thread timing: sort every row of the
+    // transpose (by source row, which is unique within it)
+    parallel_for((uint64_t)n_cols, threads, 1 << 12, [&](uint64_t a, uint64_t b) {
+        std::vector<std::pair<int32_t, float>> tmp;
+        for (uint64_t c = a; c < b; ++c) {
+            const int64_t lo = tp[c], hi = tp[c + 1];
+            if (!val) {
+                std::sort(tc.begin() + lo, tc.begin() + hi);
+                continue;
+            }
+            tmp.resize((size_t)(hi - lo));
+            for (int64_t q = lo; q < hi; ++q) tmp[(size_t)(q - lo)] = {tc[(size_t)q], tv[(size_t)q]};
+            std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+            for (int64_t q = lo; q < hi; ++q) {
+                tc[(size_t)q] = tmp[(size_t)(q - lo)].first;
+                tv[(size_t)q] = tmp[(size_t)(q - lo)].second;
+            }
+        }
+    });
+    return SPMM_OK;
+}
+
 spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* col,
                               const float* val, bool validate, std::string& err) {
     const int64_t n = H.n_rows;

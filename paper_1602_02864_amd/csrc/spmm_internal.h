@@ -175,6 +175,11 @@ inline int kc_cap(const Handle& H) {
 spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* col,
                               const float* val, bool validate, std::string& err);
 spmm_status_t encode(Handle& H, std::string& err);
+// CSR of the transpose of an n_rows x n_cols CSR (rows ascending within each
+// row of the result; duplicates kept), with range checks on the input.
+spmm_status_t transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr, const int32_t* col,
+                            const float* val, uint32_t threads, std::vector<int64_t>& tp, std::vector<int32_t>& tc,
+                            std::vector<float>& tv, std::string& err);
 spmm_status_t decode(const Handle& H, int64_t* row_ptr, int32_t* col, float* val, std::string& err);
 void tile_features(const Handle& H, int k, int xbytes, float* out);
 spmm_status_t model_tiles(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr,

@@ -166,3 +166,48 @@ def test_read_probe_rejects_bad_arguments():
     assert L.spmm_read_probe(None, 16, None, None) == pk.SPMM_EINVAL
     assert L.spmm_read_probe(16, 15, 16, None) == pk.SPMM_EINVAL     # not a multiple of 16
     assert L.spmm_read_probe(8, 16, 16, None) == pk.SPMM_EINVAL      # misaligned
+
+
+def _transpose_ref(rp, col, val, n_cols):
+    rows = np.repeat(np.arange(rp.shape[0] - 1, dtype=np.int64), np.diff(rp))
+    order = np.lexsort((rows, col.astype(np.int64)))
+    tp = np.concatenate([[0], np.cumsum(np.bincount(col, minlength=n_cols))]).astype(np.int64)
+    return tp, rows[order].astype(np.int32), None if val is None else val[order]
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_transposed_build_decodes_to_the_transpose(weighted):
+    rng = np.random.default_rng(3)
+    n, m = 700, 1300                                  # rectangular: A is n x m
+    dense = (rng.random((n, m)) < 0.01)
+    rp = np.concatenate([[0], np.cumsum(dense.sum(1))]).astype(np.int64)
+    col = np.nonzero(dense)[1].astype(np.int32)
+    val = rng.random(col.shape[0]).astype(np.float32) + 0.5 if weighted else None
+    h = pk.spmm_build_tiles(rp, col, val, n_cols=m, transpose=True, tile_rows=32, tile_cols=256)
+    assert (h.n_rows, h.n_cols) == (m, n)
+    st = pk.spmm_get_stats(h)
+    assert (st["n_rows"], st["n_cols"], st["nnz"]) == (m, n, col.shape[0])
+    tp, tc, tv = _transpose_ref(rp, col, val, m)
+    got = pk.spmm_decode_tiles(h, col.shape[0], weighted=weighted)
+    assert np.array_equal(got[0], tp) and np.array_equal(got[1], tc)
+    if weighted:
+        assert np.array_equal(got[2], tv)
+    h.close()
+    # the R-MAT graph: the transpose of the transpose is the graph
+    rp2, col2 = synth.rmat_csr(12, 8, seed=6)
+    ht = pk.spmm_build_tiles(rp2, col2, transpose=True)
+    trp, tcol = pk.spmm_decode_tiles(ht, col2.shape[0])
+    htt = pk.spmm_build_tiles(trp, tcol, transpose=True)
+    rrp, rcol = pk.spmm_decode_tiles(htt, col2.shape[0])
+    assert np.array_equal(rrp, rp2) and np.array_equal(rcol, col2)
+    ht.close()
+    htt.close()
+
+
+def test_transposed_build_checks_input():
+    rp, col = synth.small_random_csr(20, 0.2, 1)
+    bad = col.copy()
+    bad[0] = 25
+    with pytest.raises(pk.SpmmError) as ei:
+        pk.spmm_build_tiles(rp, bad, transpose=True)
+    assert ei.value.status == pk.SPMM_EINVAL

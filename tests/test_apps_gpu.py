@@ -81,3 +81,28 @@ def test_nmf_matches_oracle(symmetric):
     assert oracle.frob_rel_err(W.cpu().numpy(), Wr) <= 1e-4
     assert oracle.frob_rel_err(H.cpu().numpy(), Hr) <= 1e-4
     assert W.min().item() >= 0 and H.min().item() >= 0
+
+
+def test_directed_apps_with_transposed_handle():
+    """PageRank and NMF on a directed graph with A^T tiled by the library
+    (build option transpose) instead of a caller-side transpose."""
+    import torch
+    rp, col = synth.rmat_csr(14, 8, seed=2)
+    n = rp.shape[0] - 1
+    hT = pk.spmm_build_tiles(rp, col, transpose=True)      # row u = in-neighbours of u
+    pr, _ = _pr_gpu(hT, n)
+    ref, _ = oracle.pagerank(rp, col, n, iters=30)
+    assert _rel_l1(pr, ref) <= 1e-5 and abs(pr.sum() - 1.0) <= 1e-5
+    hA = pk.spmm_build_tiles(rp, col)
+    W0 = synth.uniform(n, 8, seed=synth.SEED_W)
+    H0 = synth.uniform(n, 8, seed=synth.SEED_H)
+    W = torch.from_numpy(W0).cuda()
+    H = torch.from_numpy(H0).cuda()
+    pk.spmm_nmf(hA, hT, W, H, iters=10)
+    torch.cuda.synchronize()
+    AT = transpose_csr(rp, col, None, n)
+    Wr, Hr = oracle.nmf(rp, col, None, W0, H0, iters=10, eps=1e-9, AT=AT)
+    assert oracle.frob_rel_err(W.cpu().numpy(), Wr) <= 1e-4
+    assert oracle.frob_rel_err(H.cpu().numpy(), Hr) <= 1e-4
+    hT.close()
+    hA.close()
