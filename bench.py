@@ -156,10 +156,13 @@ def main() -> int:
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="run a plain device copy of this many GiB first (counter calibration)")
     ap.add_argument("--mode", default="spmm",
-                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps "
+                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps | eigs "
                          "(comma-separated)")
     ap.add_argument("--stream-kib", type=int, default=0, help="streamed mode: bytes per transfer group")
     ap.add_argument("--ring-depth", type=int, default=0, help="streamed mode: device ring slots")
+    ap.add_argument("--eig-blocks", default="1,2,4", help="eigs mode: block sizes")
+    ap.add_argument("--nev", type=int, default=8, help="eigs mode: eigenpairs wanted")
+    ap.add_argument("--eig-tol", type=float, default=1e-5, help="eigs mode: relative residual tolerance")
     args = ap.parse_args()
     modes = args.mode.split(",")
     if args.gpus == 1 and modes != ["spmm"]:
@@ -485,7 +488,7 @@ def run_other_modes(args, modes) -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.init()
-    big = any(m in ("precision", "apps") for m in modes)
+    big = any(m in ("precision", "apps", "eigs") for m in modes)
     scale = args.scale if args.scale is not None else (26 if big else 25)
     ef = args.edge_factor if args.edge_factor is not None else (28.0 if big else 44.0)
     sym = big
@@ -728,6 +731,48 @@ def run_other_modes(args, modes) -> int:
             out["learned_over_plain_pagerank"] = round(out["plain"]["pagerank_ms_per_iter"] /
                                                        out["learned"]["pagerank_ms_per_iter"], 4)
             out["learned_over_plain_nmf"] = round(out["plain"]["nmf_ms_per_iter"] / out["learned"]["nmf_ms_per_iter"], 4)
+            print(json.dumps(out), flush=True)
+        elif mode == "eigs":
+            # eight largest-magnitude eigenpairs of the undirected graph
+            # (Section 4.2's experiment), for each block size
+            nev = args.nev
+            h = pk.spmm_build_tiles(rp, col, validate=False)
+            out = {"mode": "eigs", "metric": f"time to {nev} eigenpairs (block Krylov-Schur, LM)", "n_gpus": 1,
+                   "data": "synthetic", "config": {"workload": workload, "n": n, "nnz": nnz, "nev": nev,
+                                                   "tol": args.eig_tol}}
+            sel = sample_rows(rp, n, 20_000_000)
+            for b in [int(x) for x in args.eig_blocks.split(",")]:
+                Xw = torch.from_numpy(synth.uniform(n, b, seed=synth.SEED_X)).to(dev)
+                Yw = torch.empty((n, b), device=dev)
+                spmm_ms = kernel_ms(h, lambda: pk.spmm_run(h, Xw, Yw, stream=stream))
+                del Xw, Yw
+                V = torch.empty((n, nev), device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                evals, resid, info = pk.spmm_eigs(h, nev, block=b, tol=args.eig_tol, evecs=V, seed=7)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                Vd = V.double()
+                orth = float((Vd.T @ Vd - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max().item())
+                del Vd
+                Vh = V.cpu().numpy()
+                r_sel = oracle.eig_residuals(rp, col, None, evals, Vh, sel) / np.abs(evals)
+                res = {"block": b, "max_dim": info["max_dim"], "seconds": round(wall, 3),
+                       "n_spmm": info["n_spmm"], "restarts": info["restarts"],
+                       "spmm_s": round(info["spmm_ms"] / 1e3, 3),
+                       "spmm_share": round(info["spmm_ms"] / 1e3 / wall, 4),
+                       "spmm_k_ms": round(spmm_ms, 3),
+                       "evals": [float(x) for x in evals],
+                       "resid_est_max": float(resid.max()),
+                       "sampled_resid_rel_max": float(r_sel.max()),
+                       "orth_max": orth,
+                       "ok": bool(info["n_converged"] == nev and r_sel.max() <= 4 * args.eig_tol + 2e-6
+                                  and orth < 1e-5)}
+                out[f"block{b}"] = res
+                log(f"eigs block {b}: {res}")
+                del V, Vh
+            h.close()
+            out["sampled_rows"] = int(sel.size)
             print(json.dumps(out), flush=True)
         else:
             raise SystemExit(f"unknown mode {mode}")

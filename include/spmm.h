@@ -41,7 +41,8 @@ typedef enum {
     SPMM_ENOMEM = -2,        /* host or device allocation failed              */
     SPMM_EHIP = -3,          /* a HIP runtime call failed                     */
     SPMM_EUNSUPPORTED = -4,  /* valid request this build does not support     */
-    SPMM_ESTATE = -5         /* handle is in the wrong state for this call    */
+    SPMM_ESTATE = -5,        /* handle is in the wrong state for this call    */
+    SPMM_ENOTCONV = -6       /* an iterative method stopped before converging */
 } spmm_status_t;
 
 /* Element type of X.  Accumulation is always FP32 and Y is always FP32. */
@@ -485,6 +486,81 @@ spmm_status_t spmm_selector_train(const float* feat, const float* target, const 
  *   params: host float[PARAMS].  Synchronous.
  */
 spmm_status_t spmm_select_learned(spmm_handle_t h, const float* params, int k, spmm_xdtype_t dt);
+
+/* ---------------------------------------------------------------------------
+ * Eigensolver (Section 4.2): a few eigenpairs of a symmetric sparse matrix
+ * by the block Krylov-Schur method, every sparse product an SpMM with k =
+ * block columns.
+ * ------------------------------------------------------------------------- */
+#define SPMM_EIGS_LM 0  /* largest magnitude */
+#define SPMM_EIGS_LA 1  /* largest algebraic */
+#define SPMM_EIGS_SA 2  /* smallest algebraic */
+
+typedef struct {
+    int32_t nev;          /* eigenpairs wanted, >= 1                                   */
+    int32_t block;        /* block size b (vectors per SpMM), 1..16; 0 -> 4            */
+    int32_t max_dim;      /* basis columns m before a restart: a multiple of b with
+                             m >= nev + b, m + b <= n, m * b <= 1024 and
+                             m + b <= 512;
+                             0 -> the smallest multiple of b >= max(6 nev, nev + 4b),
+                             lowered to the limits                                 */
+    int32_t which;        /* SPMM_EIGS_LM / _LA / _SA                                  */
+    int32_t max_restarts; /* 0 -> 500                                                  */
+    int32_t reserved;     /* 0                                                         */
+    double tol;           /* converged when ||A y - theta y|| <= tol |theta|; 0 -> 1e-5 */
+    uint64_t seed;        /* starting block (and any replacement block): uniform
+                             [-1/2, 1/2) from SplitMix64 of (seed, row, column)       */
+} spmm_eigs_opts;
+
+typedef struct {
+    int32_t n_converged;  /* wanted pairs whose residual estimate met tol  */
+    int32_t restarts;
+    int64_t n_spmm;       /* SpMM calls (each with k = block)              */
+    double spmm_ms;       /* device time of the SpMM calls (HIP events)    */
+    double total_ms;      /* wall-clock time of the whole call             */
+    int32_t max_dim;      /* m and b actually used                         */
+    int32_t block;
+} spmm_eigs_info;
+
+/*
+ * Eigenpairs of a symmetric A (handle built from a symmetric CSR; symmetry
+ * is not checked) with the block Krylov-Schur method: an orthonormal basis
+ * V (n x (m + b) FP32 in HBM) grows one block at a time (W = A V_j by
+ * spmm_run, projected out of V twice in FP64 arithmetic, then made
+ * orthonormal by two SVQB passes), T = V^T A V is kept on the host in FP64,
+ * and after m columns the Ritz pairs of T (cyclic Jacobi) decide: stop when
+ * the nev wanted ones have residual estimates <= tol |theta|, else keep the
+ * best p ~ (m + nev) / 2 Ritz vectors and the residual block and expand
+ * again (thick restart).  Directions of W lost to cancellation (an invariant
+ * subspace) are replaced by random vectors orthogonal to V.
+ *   h      : square, tiles in HBM (SPMM_PLACE_DEVICE).
+ *   evals  : host double[nev], wanted end first (|theta| descending for LM,
+ *            ties by value descending).
+ *   evecs  : device float n x nev (row stride ldvec >= nev): unit Ritz
+ *            vectors in the order of evals; or NULL.
+ *   resid  : host double[nev], residual estimates ||A y - theta y|| / |theta|
+ *            (absolute if theta = 0); or NULL.
+ *   info   : or NULL.
+ * Device workspace: three n x round_up(m + b, 4) FP32 and one n x b FP32
+ * buffers plus 8 MiB, allocated per call.  Synchronous (several host
+ * round trips per block).  Errors: SPMM_EINVAL, SPMM_ESTATE (tiles in host
+ * memory), SPMM_ENOMEM, SPMM_EHIP, SPMM_ENOTCONV (max_restarts reached:
+ * evals, evecs, resid and info hold the current Ritz pairs; or, with the
+ * message saying so, a replacement block came out rank deficient: outputs
+ * unspecified).
+ */
+spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* opts, double* evals, float* evecs, int64_t ldvec,
+                        double* resid, spmm_eigs_info* info, hipStream_t s);
+
+/*
+ * Host helper: all eigenpairs of a small dense symmetric matrix by the
+ * cyclic Jacobi method, the Rayleigh-Ritz step spmm_eigs applies to T.
+ *   a : host double n x n row-major, exactly symmetric (else SPMM_EINVAL).
+ *   w : host double[n], ascending.   z : host double n x n row-major,
+ *       column j the unit eigenvector of w[j].
+ * 1 <= n <= 4096.  No device work.
+ */
+spmm_status_t spmm_sym_eig_small(int n, const double* a, double* w, double* z);
 
 #ifdef __cplusplus
 }

@@ -15,6 +15,9 @@ Floating point is FP64 throughout unless a function says otherwise.
   definitions (C).
 * ``pagerank`` -- the PageRank update of Section 4.1 (power iteration).
 * ``nmf`` -- the multiplicative updates of Section 4.3, H first, then W.
+* ``sym_eigs`` / ``eig_residuals`` -- wanted eigenpairs of a symmetric A
+  (Section 4.2's eigensolver) from the dense FP64 eigen-decomposition, and
+  the residuals ||A v - lambda v|| of given pairs.
 * ``mlp_*`` / ``adam_step`` -- the tile-selector cost model (8 -> 64 -> 64
   -> V, ReLU), masked MSE loss, its gradients and the Adam update.
 * ``scsr_bytes`` / ``dcsc_bytes`` -- the per-tile storage sizes of
@@ -288,6 +291,61 @@ def nmf_objective(row_ptr, col, val, W, H) -> float:
     W = np.asarray(W, np.float64)
     H = np.asarray(H, np.float64)
     return a2 - 2.0 * float(np.sum(W * AH)) + float(np.sum((W.T @ W) * (H.T @ H)))
+
+
+# ------------------------------------------------------------ eigensolver
+
+def _which_order(w, which: str):
+    """Indices of w with the wanted end first: "LM" |w| descending (equal
+    magnitudes: larger value first), "LA" descending, "SA" ascending."""
+    w = np.asarray(w, dtype=np.float64)
+    if which == "LM":
+        return np.lexsort((-w, -np.abs(w)))
+    if which == "LA":
+        return np.argsort(-w, kind="stable")
+    if which == "SA":
+        return np.argsort(w, kind="stable")
+    raise ValueError(which)
+
+
+def dense(row_ptr, col, val, n_cols: int | None = None) -> np.ndarray:
+    """The CSR matrix as a dense FP64 array (small matrices only)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    n = len(row_ptr) - 1
+    A = np.zeros((n, n if n_cols is None else n_cols), dtype=np.float64)
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    v = np.ones(len(col)) if val is None else np.asarray(val, dtype=np.float64)
+    np.add.at(A, (rows, np.asarray(col, dtype=np.int64)), v)
+    return A
+
+
+def sym_eigs(row_ptr, col, val, nev: int, which: str = "LM"):
+    """The nev wanted eigenpairs of a symmetric sparse A (the quantity the
+    eigensolver of Section 4.2 computes), by definition: the full FP64
+    eigen-decomposition of the dense matrix (numpy.linalg.eigh), ordered as
+    in _which_order.  Returns (values, unit eigenvectors as columns).  Small
+    n only; raises if A is not symmetric."""
+    A = dense(row_ptr, col, val)
+    if not np.array_equal(A, A.T):
+        raise ValueError("A is not symmetric")
+    w, Z = np.linalg.eigh(A)
+    o = _which_order(w, which)[:nev]
+    return w[o], Z[:, o]
+
+
+def eig_residuals(row_ptr, col, val, lam, V, rows=None) -> np.ndarray:
+    """||(A V)[rows, j] - lam_j V[rows, j]||_2 per column j, in FP64 (all
+    rows if rows is None).  V: n x nev, the full vectors (A V needs every
+    neighbour's entry)."""
+    V = np.asarray(V)
+    lam = np.asarray(lam, dtype=np.float64)
+    if rows is None:
+        AV = spmm(row_ptr, col, val, V)
+        Vr = np.asarray(V, dtype=np.float64)
+    else:
+        AV = spmm_sel(row_ptr, col, val, V, rows)
+        Vr = np.asarray(V[np.asarray(rows)], dtype=np.float64)
+    return np.sqrt(np.sum((AV - Vr * lam[None, :]) ** 2, axis=0))
 
 
 # -------------------------------------------------------------------- MLP

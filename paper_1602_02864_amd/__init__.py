@@ -20,6 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "spmm.h")
 
 # spmm_status_t
 SPMM_OK, SPMM_EINVAL, SPMM_ENOMEM, SPMM_EHIP, SPMM_EUNSUPPORTED, SPMM_ESTATE = 0, -1, -2, -3, -4, -5
+SPMM_ENOTCONV = -6
 # spmm_xdtype_t
 SPMM_X_F32, SPMM_X_BF16, SPMM_X_FP8_E4M3 = 0, 1, 2
 # spmm_variant_t
@@ -42,7 +43,10 @@ SPMM_MLP_OFF_B3 = SPMM_MLP_OFF_W3 + SPMM_MLP_HIDDEN * SPMM_NUM_VARIANTS
 SPMM_MLP_PARAMS = SPMM_MLP_OFF_B3 + SPMM_NUM_VARIANTS
 
 _STATUS_NAMES = {0: "SPMM_OK", -1: "SPMM_EINVAL", -2: "SPMM_ENOMEM", -3: "SPMM_EHIP",
-                 -4: "SPMM_EUNSUPPORTED", -5: "SPMM_ESTATE"}
+                 -4: "SPMM_EUNSUPPORTED", -5: "SPMM_ESTATE", -6: "SPMM_ENOTCONV"}
+# eigensolver: wanted end of the spectrum
+SPMM_EIGS_LM, SPMM_EIGS_LA, SPMM_EIGS_SA = 0, 1, 2
+_WHICH = {"LM": SPMM_EIGS_LM, "LA": SPMM_EIGS_LA, "SA": SPMM_EIGS_SA}
 
 
 class SpmmError(RuntimeError):
@@ -79,6 +83,18 @@ class spmm_train_opts(ctypes.Structure):
 
 
 _lib = None
+
+
+class spmm_eigs_opts(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int32), ("block", ctypes.c_int32), ("max_dim", ctypes.c_int32),
+                ("which", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class spmm_eigs_info(ctypes.Structure):
+    _fields_ = [("n_converged", ctypes.c_int32), ("restarts", ctypes.c_int32), ("n_spmm", ctypes.c_int64),
+                ("spmm_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("max_dim", ctypes.c_int32),
+                ("block", ctypes.c_int32)]
 
 
 def load_library():
@@ -137,7 +153,9 @@ def load_library():
             ("spmm_timing_begin", [vp]),
             ("spmm_stream_run_host", [vp, vp, i32, i64, vp, i64, i32, ctypes.c_uint32]),
             ("spmm_read_probe", [vp, ctypes.c_uint64, vp, vp]),
-            ("spmm_timing_end", [vp, vp, vp])]:
+            ("spmm_timing_end", [vp, vp, vp]),
+            ("spmm_eigs", [vp, ctypes.POINTER(spmm_eigs_opts), vp, vp, i64, vp, ctypes.POINTER(spmm_eigs_info), vp]),
+            ("spmm_sym_eig_small", [i32, vp, vp, vp])]:
         fn = getattr(L, name)
         fn.restype = i32
         fn.argtypes = args
@@ -511,3 +529,50 @@ def spmm_selector_train(feat, target, mask=None, params=None, *, epochs: int = 0
 def spmm_select_learned(h: Handle, params, k: int, dtype: int = SPMM_X_F32) -> None:
     p = _host(params, np.float32)
     _check(load_library().spmm_select_learned(h.ptr, p.ctypes.data, int(k), int(dtype)), "spmm_select_learned")
+
+
+def spmm_eigs(h: Handle, nev: int, *, block: int = 4, max_dim: int = 0, which: str = "LM", tol: float = 0.0,
+              max_restarts: int = 0, seed: int = 1, evecs=None, stream=None, check: bool = True):
+    """Eigenpairs of a symmetric A by the block Krylov-Schur method.
+
+    evecs: device float32 tensor n x nev (row-major) for the Ritz vectors, or
+    None.  Returns (evals, resid, info): evals and resid are float64 arrays in
+    the order of the wanted end ("LM", "LA" or "SA"), resid the relative
+    residual estimates.  With check=False a run that stops before converging
+    (SPMM_ENOTCONV) returns its current Ritz pairs instead of raising.
+    """
+    if which not in _WHICH:
+        raise ValueError(f"which must be one of {sorted(_WHICH)}")
+    o = spmm_eigs_opts(nev=int(nev), block=int(block), max_dim=int(max_dim), which=_WHICH[which],
+                       max_restarts=int(max_restarts), reserved=0, tol=float(tol), seed=int(seed) & (2 ** 64 - 1))
+    evals = np.zeros(max(int(nev), 0), dtype=np.float64)
+    resid = np.zeros_like(evals)
+    info = spmm_eigs_info()
+    ldvec = 0
+    if evecs is not None:
+        if hasattr(evecs, "shape"):
+            if tuple(evecs.shape[:1]) != (h.n_rows,) or evecs.shape[1] < nev or evecs.stride(1) != 1:
+                raise ValueError("evecs must be n x (>= nev) with unit column stride")
+            if str(evecs.dtype) != "torch.float32" or not evecs.is_cuda:
+                raise TypeError("evecs must be a float32 device tensor")
+            ldvec = int(evecs.stride(0))
+        else:
+            ldvec = int(nev)
+    st = load_library().spmm_eigs(h.ptr, ctypes.byref(o), evals.ctypes.data, _ptr(evecs), ldvec,
+                                  resid.ctypes.data, ctypes.byref(info), _stream(stream, evecs))
+    if st != SPMM_OK and not (st == SPMM_ENOTCONV and not check):
+        _check(st, "spmm_eigs")
+    return evals, resid, {f: getattr(info, f) for f, _ in spmm_eigs_info._fields_}
+
+
+def spmm_sym_eig_small(a):
+    """All eigenpairs of a small dense symmetric matrix (cyclic Jacobi, host):
+    (w ascending, z with unit eigenvectors in its columns)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    if a.shape != (n, n):
+        raise ValueError("a must be square")
+    w = np.zeros(n)
+    z = np.zeros((n, n))
+    _check(load_library().spmm_sym_eig_small(n, a.ctypes.data, w.ctypes.data, z.ctypes.data), "spmm_sym_eig_small")
+    return w, z

@@ -245,6 +245,19 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int np, flo
 // probe_kernels.hip: one streaming read of bytes (a multiple of 16) at buf
 hipError_t launch_read_probe(const void* buf, uint64_t bytes, float* sink, hipStream_t s);
 
+// Tall-skinny dense kernels of the eigensolver (FP32 data, FP64 arithmetic).
+int ts_max_outputs();          // largest p * q launch_ts_tn accepts
+int ts_max_width();            // largest p + q launch_ts_tn accepts
+size_t ts_partial_doubles();   // size of the part buffer launch_ts_tn needs
+// C (p x q FP64, row-major) = A^T B; A n x p (stride lda), B n x q (stride ldb).
+hipError_t launch_ts_tn(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q, int64_t n,
+                        double* part, double* C, hipStream_t s);
+// W = alpha W + beta A C; A n x p, C p x q FP64, W n x q (must not alias A).
+hipError_t launch_ts_nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta,
+                        float* W, int64_t ldw, int64_t n, hipStream_t s);
+// X[i][c] (c < q <= 64) uniform in [-1/2, 1/2), a function of (seed, i, c).
+hipError_t launch_fill_uniform(float* X, int64_t ldx, int q, int64_t n, uint64_t seed, hipStream_t s);
+
 // quant_kernels.hip
 hipError_t launch_quantize(const float* X, int64_t n, int k, int64_t ldx, int dtype, void* Xq,
                            int64_t ldq, float* col_scale, bool scales_given, hipStream_t s);
