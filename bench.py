@@ -156,13 +156,14 @@ def main() -> int:
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="run a plain device copy of this many GiB first (counter calibration)")
     ap.add_argument("--mode", default="spmm",
-                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps | eigs "
+                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps | eigs | dense "
                          "(comma-separated)")
     ap.add_argument("--stream-kib", type=int, default=0, help="streamed mode: bytes per transfer group")
     ap.add_argument("--ring-depth", type=int, default=0, help="streamed mode: device ring slots")
-    ap.add_argument("--eig-blocks", default="1,2,4", help="eigs mode: block sizes")
+    ap.add_argument("--eig-blocks", default="1,2,4,8", help="eigs mode: block sizes")
     ap.add_argument("--nev", type=int, default=8, help="eigs mode: eigenpairs wanted")
     ap.add_argument("--eig-tol", type=float, default=1e-5, help="eigs mode: relative residual tolerance")
+    ap.add_argument("--no-sem", action="store_true", help="eigs mode: skip the semi-external runs")
     args = ap.parse_args()
     modes = args.mode.split(",")
     if args.gpus == 1 and modes != ["spmm"]:
@@ -488,13 +489,17 @@ def run_other_modes(args, modes) -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.init()
-    big = any(m in ("precision", "apps", "eigs") for m in modes)
+    big = any(m in ("precision", "apps", "eigs", "dense") for m in modes)
     scale = args.scale if args.scale is not None else (26 if big else 25)
     ef = args.edge_factor if args.edge_factor is not None else (28.0 if big else 44.0)
     sym = big
     t0 = time.perf_counter()
-    rp, col = synth.rmat_csr(scale, ef, seed=synth.SEED_GRAPH, symmetrize=sym, progress=log)
-    n, nnz = rp.shape[0] - 1, int(col.shape[0])
+    if modes == ["dense"]:          # only the row count matters
+        rp, col = np.zeros(2, np.int64), np.zeros(0, np.int32)
+        n, nnz = 1 << scale, 0
+    else:
+        rp, col = synth.rmat_csr(scale, ef, seed=synth.SEED_GRAPH, symmetrize=sym, progress=log)
+        n, nnz = rp.shape[0] - 1, int(col.shape[0])
     workload = f"rmat-s{scale}-ef{int(ef)}-{'symmetrised' if sym else 'directed'}"
     log(f"graph {workload}: n={n} nnz={nnz} ({time.perf_counter() - t0:.1f}s)")
     stream = torch.cuda.current_stream(dev)
@@ -732,6 +737,58 @@ def run_other_modes(args, modes) -> int:
                                                        out["learned"]["pagerank_ms_per_iter"], 4)
             out["learned_over_plain_nmf"] = round(out["plain"]["nmf_ms_per_iter"] / out["learned"]["nmf_ms_per_iter"], 4)
             print(json.dumps(out), flush=True)
+        elif mode == "dense":
+            # the eigensolver's tall-skinny products on n rows of the graph's
+            # size, basis stride as the solver lays it out; HBM GB/s from
+            # the algorithmic bytes
+            import itertools
+            out = {"mode": "dense", "metric": "tall-skinny basis products, algorithmic GB/s", "n_gpus": 1,
+                   "data": "synthetic", "config": {"n": n}, "shapes": []}
+            ld = 136
+            A = torch.rand((n, ld), device=dev)
+            B = torch.rand((n, 16), device=dev)
+            W = torch.rand((n, 64), device=dev)
+            work = torch.empty(pk.spmm_dense_tn_workspace(n, 512, 2) // 8, dtype=torch.float64, device=dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            for p_, q_ in itertools.product((8, 32, 64, 128), (1, 4, 8)):
+                C = torch.rand((p_, q_), dtype=torch.float64, device=dev)
+                Bq = B[:, :q_]
+                res = {"p": p_, "q": q_}
+                for name, fn, nbytes in (
+                        ("tn", lambda: pk.spmm_dense_tn(A, Bq, C, work, p=p_, q=q_, stream=stream),
+                         4.0 * n * (p_ + q_)),
+                        ("nn", lambda: pk.spmm_dense_nn(A, C, W, alpha=1.0, beta=-1.0, p=p_, q=q_, stream=stream),
+                         4.0 * n * (p_ + 2 * q_))):
+                    fn()
+                    e0.record(stream)
+                    for _ in range(5):
+                        fn()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / 5
+                    res[name + "_ms"] = round(ms, 3)
+                    res[name + "_gbs"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+                out["shapes"].append(res)
+                log(f"dense {res}")
+            # the restart product: basis (m + b columns) times the kept Ritz vectors
+            for m_, q_ in ((48, 32), (96, 56), (128, 72)):
+                C = torch.rand((m_ + 8, q_), dtype=torch.float64, device=dev)
+                Wr = torch.empty((n, q_), device=dev)
+                fn = lambda: pk.spmm_dense_nn(A, C, Wr, p=m_ + 8, q=q_, stream=stream)
+                fn()
+                e0.record(stream)
+                for _ in range(3):
+                    fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 3
+                res = {"restart_p": m_ + 8, "q": q_, "ms": round(ms, 3),
+                       "gbs": round(4.0 * n * (m_ + 8 + q_) / (ms * 1e-3) / 1e9, 1)}
+                out["shapes"].append(res)
+                log(f"dense {res}")
+                del Wr
+            del A, B, W, work
+            print(json.dumps(out), flush=True)
         elif mode == "eigs":
             # eight largest-magnitude eigenpairs of the undirected graph
             # (Section 4.2's experiment), for each block size
@@ -753,8 +810,9 @@ def run_other_modes(args, modes) -> int:
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t0
                 Vd = V.double()
-                orth = float((Vd.T @ Vd - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max().item())
-                del Vd
+                G = torch.stack([(Vd * Vd[:, j:j + 1]).sum(0) for j in range(nev)])    # V^T V, FP64
+                orth = float((G - torch.eye(nev, dtype=torch.float64, device=dev)).abs().max().item())
+                del Vd, G
                 Vh = V.cpu().numpy()
                 r_sel = oracle.eig_residuals(rp, col, None, evals, Vh, sel) / np.abs(evals)
                 res = {"block": b, "max_dim": info["max_dim"], "seconds": round(wall, 3),
@@ -762,6 +820,9 @@ def run_other_modes(args, modes) -> int:
                        "spmm_s": round(info["spmm_ms"] / 1e3, 3),
                        "spmm_share": round(info["spmm_ms"] / 1e3 / wall, 4),
                        "spmm_k_ms": round(spmm_ms, 3),
+                       "dense_s": round(info["dense_ms"] / 1e3, 3),
+                       "dense_gbs": round(info["dense_bytes"] / (info["dense_ms"] * 1e-3) / 1e9, 1),
+                       "host_s": round((info["total_ms"] - info["spmm_ms"] - info["dense_ms"]) / 1e3, 3),
                        "evals": [float(x) for x in evals],
                        "resid_est_max": float(resid.max()),
                        "sampled_resid_rel_max": float(r_sel.max()),
@@ -772,6 +833,27 @@ def run_other_modes(args, modes) -> int:
                 log(f"eigs block {b}: {res}")
                 del V, Vh
             h.close()
+            if not args.no_sem:
+                # semi-external: tiles in pinned host memory, streamed for every
+                # product (the basis stays in HBM); identical results expected
+                hs = pk.spmm_build_tiles(rp, col, validate=False, place=pk.SPMM_PLACE_PINNED_HOST,
+                                         stream_kib=args.stream_kib, ring_depth=args.ring_depth)
+                for b in [int(x) for x in args.eig_blocks.split(",")]:
+                    V = torch.empty((n, nev), device=dev)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    evals, resid, info = pk.spmm_eigs(hs, nev, block=b, tol=args.eig_tol, evecs=V, seed=7)
+                    torch.cuda.synchronize()
+                    wall = time.perf_counter() - t0
+                    ref = out[f"block{b}"]
+                    res = {"seconds": round(wall, 3), "n_spmm": info["n_spmm"],
+                           "spmm_s": round(info["spmm_ms"] / 1e3, 3),
+                           "in_hbm_over_sem": round(ref["seconds"] / wall, 4),
+                           "evals_equal_in_hbm": [float(x) for x in evals] == ref["evals"]}
+                    out[f"sem_block{b}"] = res
+                    log(f"eigs semi-external block {b}: {res}")
+                    del V
+                hs.close()
             out["sampled_rows"] = int(sel.size)
             print(json.dumps(out), flush=True)
         else:

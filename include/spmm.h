@@ -502,8 +502,8 @@ typedef struct {
     int32_t max_dim;      /* basis columns m before a restart: a multiple of b with
                              m >= nev + b, m + b <= n, m * b <= 1024 and
                              m + b <= 512;
-                             0 -> the smallest multiple of b >= max(6 nev, nev + 4b),
-                             lowered to the limits                                 */
+                             0 -> the smallest multiple of b >= max(6 nev, nev + 4b,
+                             24 b), lowered to the limits                          */
     int32_t which;        /* SPMM_EIGS_LM / _LA / _SA                                  */
     int32_t max_restarts; /* 0 -> 500                                                  */
     int32_t reserved;     /* 0                                                         */
@@ -520,6 +520,9 @@ typedef struct {
     double total_ms;      /* wall-clock time of the whole call             */
     int32_t max_dim;      /* m and b actually used                         */
     int32_t block;
+    double dense_ms;      /* device time of the dense basis kernels (events) */
+    double dense_bytes;   /* their algorithmic HBM bytes: 4 n (p + q) for
+                             C = A^T B, 4 n (p + 2q) for W += A C            */
 } spmm_eigs_info;
 
 /*
@@ -533,7 +536,12 @@ typedef struct {
  * best p ~ (m + nev) / 2 Ritz vectors and the residual block and expand
  * again (thick restart).  Directions of W lost to cancellation (an invariant
  * subspace) are replaced by random vectors orthogonal to V.
- *   h      : square, tiles in HBM (SPMM_PLACE_DEVICE).
+ *   h      : square.  Tiles in HBM (SPMM_PLACE_DEVICE), or in pinned host
+ *            memory (SPMM_PLACE_PINNED_HOST): then every product streams
+ *            the tiles as spmm_stream_run does -- the semi-external
+ *            eigensolver of Section 4.2 with A in host DRAM and the basis in
+ *            HBM -- on two streams of the solver's own, after the work
+ *            already queued on s.  Both give identical results.
  *   evals  : host double[nev], wanted end first (|theta| descending for LM,
  *            ties by value descending).
  *   evecs  : device float n x nev (row stride ldvec >= nev): unit Ritz
@@ -541,16 +549,39 @@ typedef struct {
  *   resid  : host double[nev], residual estimates ||A y - theta y|| / |theta|
  *            (absolute if theta = 0); or NULL.
  *   info   : or NULL.
- * Device workspace: three n x round_up(m + b, 4) FP32 and one n x b FP32
- * buffers plus 8 MiB, allocated per call.  Synchronous (several host
- * round trips per block).  Errors: SPMM_EINVAL, SPMM_ESTATE (tiles in host
- * memory), SPMM_ENOMEM, SPMM_EHIP, SPMM_ENOTCONV (max_restarts reached:
+ * Device workspace: two n x round_up(m + b, 4) and two n x b FP32 buffers
+ * plus 16 MiB, allocated per call (and the handle's ring, for tiles in host
+ * memory).  Synchronous (several host
+ * round trips per block).  Errors: SPMM_EINVAL, SPMM_ENOMEM, SPMM_EHIP,
+ * SPMM_ENOTCONV (max_restarts reached:
  * evals, evecs, resid and info hold the current Ritz pairs; or, with the
  * message saying so, a replacement block came out rank deficient: outputs
  * unspecified).
  */
 spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* opts, double* evals, float* evecs, int64_t ldvec,
                         double* resid, spmm_eigs_info* info, hipStream_t s);
+
+/*
+ * The eigensolver's tall-skinny dense products, for FP32 row-major blocks
+ * of n rows (Section 4.2 notes that an eigensolver adds many dense matrix
+ * operations to the SpMMs):
+ *   spmm_dense_tn : C = A^T B.  A n x p (stride lda >= p), B n x q (stride
+ *                   ldb >= q), 1 <= p <= 512, 1 <= q <= 16, p q <= 1024.
+ *                   C: device double p x q, row-major.  Products and sums
+ *                   in FP64, summed in an order fixed by n alone (the same
+ *                   bits for the same inputs).  work: device scratch of at
+ *                   least spmm_dense_tn_workspace(n, p, q) bytes.
+ *   spmm_dense_nn : W = alpha W + beta A C.  A n x p (stride lda >= p), C
+ *                   device double p x q row-major, W n x q (stride ldw >= q;
+ *                   must not overlap A).  FP64 sums, FP32 store; W is not
+ *                   read when alpha = 0.
+ * Asynchronous on s.  Errors: SPMM_EINVAL, SPMM_EHIP.
+ */
+size_t spmm_dense_tn_workspace(int64_t n, int p, int q);
+spmm_status_t spmm_dense_tn(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q, int64_t n,
+                            double* C, void* work, size_t work_bytes, hipStream_t s);
+spmm_status_t spmm_dense_nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta,
+                            float* W, int64_t ldw, int64_t n, hipStream_t s);
 
 /*
  * Host helper: all eigenpairs of a small dense symmetric matrix by the

@@ -94,7 +94,7 @@ class spmm_eigs_opts(ctypes.Structure):
 class spmm_eigs_info(ctypes.Structure):
     _fields_ = [("n_converged", ctypes.c_int32), ("restarts", ctypes.c_int32), ("n_spmm", ctypes.c_int64),
                 ("spmm_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("max_dim", ctypes.c_int32),
-                ("block", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("dense_ms", ctypes.c_double), ("dense_bytes", ctypes.c_double)]
 
 
 def load_library():
@@ -155,10 +155,14 @@ def load_library():
             ("spmm_read_probe", [vp, ctypes.c_uint64, vp, vp]),
             ("spmm_timing_end", [vp, vp, vp]),
             ("spmm_eigs", [vp, ctypes.POINTER(spmm_eigs_opts), vp, vp, i64, vp, ctypes.POINTER(spmm_eigs_info), vp]),
-            ("spmm_sym_eig_small", [i32, vp, vp, vp])]:
+            ("spmm_sym_eig_small", [i32, vp, vp, vp]),
+            ("spmm_dense_tn", [vp, i64, i32, vp, i64, i32, i64, vp, vp, ctypes.c_size_t, vp]),
+            ("spmm_dense_nn", [vp, i64, i32, vp, i32, ctypes.c_double, ctypes.c_double, vp, i64, i64, vp])]:
         fn = getattr(L, name)
         fn.restype = i32
         fn.argtypes = args
+    L.spmm_dense_tn_workspace.restype = ctypes.c_size_t
+    L.spmm_dense_tn_workspace.argtypes = [i64, i32, i32]
     del u32
     _lib = L
     return L
@@ -576,3 +580,30 @@ def spmm_sym_eig_small(a):
     z = np.zeros((n, n))
     _check(load_library().spmm_sym_eig_small(n, a.ctypes.data, w.ctypes.data, z.ctypes.data), "spmm_sym_eig_small")
     return w, z
+
+
+def spmm_dense_tn_workspace(n: int, p: int, q: int) -> int:
+    return int(load_library().spmm_dense_tn_workspace(int(n), int(p), int(q)))
+
+
+def spmm_dense_tn(A, B, C, work, p: int | None = None, q: int | None = None, stream=None) -> None:
+    """C = A^T B (FP64) for device FP32 row-major A (n x >= p) and B (n x >= q)."""
+    p = A.shape[1] if p is None else p
+    q = B.shape[1] if q is None else q
+    n = A.shape[0]
+    lda, ldb = (int(A.stride(0)), int(B.stride(0))) if n > 0 else (p, q)     # no rows: any stride
+    st = load_library().spmm_dense_tn(_ptr(A), lda, int(p), _ptr(B), ldb, int(q), int(n),
+                                      _ptr(C), _ptr(work), int(work.numel() * work.element_size()),
+                                      _stream(stream, A))
+    _check(st, "spmm_dense_tn")
+
+
+def spmm_dense_nn(A, C, W, alpha: float = 0.0, beta: float = 1.0, p: int | None = None, q: int | None = None,
+                  stream=None) -> None:
+    """W = alpha W + beta A C for device FP32 A (n x >= p), FP64 C (p x q), FP32 W (n x >= q)."""
+    p = A.shape[1] if p is None else p
+    q = W.shape[1] if q is None else q
+    lda, ldw = (int(A.stride(0)), int(W.stride(0))) if A.shape[0] > 0 else (p, q)
+    st = load_library().spmm_dense_nn(_ptr(A), lda, int(p), _ptr(C), int(q), float(alpha), float(beta),
+                                      _ptr(W), ldw, int(A.shape[0]), _stream(stream, A))
+    _check(st, "spmm_dense_nn")

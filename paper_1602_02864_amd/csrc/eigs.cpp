@@ -92,8 +92,10 @@ uint64_t mix64(uint64_t z) {  // SplitMix64 finaliser: seeds of successive rando
 constexpr double kRankTol = 1e-12;
 
 struct Solver {
+    spmm_handle_t h;
     spmm::Handle& H;
     hipStream_t s;
+    hipStream_t copy = nullptr;  // tiles in host memory: the stream of the tile copies
     int64_t n;
     int b, m, ldv;
     float* V[2];
@@ -107,6 +109,32 @@ struct Solver {
     int64_t n_spmm = 0;
     double spmm_ms = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // dense kernels: an event pair around each launch (read back at the end)
+    // and the algorithmic HBM bytes of each
+    std::vector<hipEvent_t> dense_ev;
+    size_t dense_used = 0;
+    double dense_bytes = 0.0;
+
+    hipError_t dense_mark() {
+        if (dense_used == dense_ev.size()) {
+            hipEvent_t e = nullptr;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            dense_ev.push_back(e);
+        }
+        return hipEventRecord(dense_ev[dense_used++], s);
+    }
+    spmm_status_t dense_ms(double& ms) {
+        ms = 0.0;
+        for (size_t i = 0; i + 1 < dense_used; i += 2) {
+            hipError_t e = hipEventSynchronize(dense_ev[i + 1]);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, dense_ev[i], dense_ev[i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "dense kernel timing");
+            ms += t;
+        }
+        return SPMM_OK;
+    }
 
     spmm_status_t sync(const char* what) {
         hipError_t e = hipStreamSynchronize(s);
@@ -123,12 +151,18 @@ struct Solver {
         return sync("copy to device");
     }
     spmm_status_t tn(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q, double* C) {
-        hipError_t e = spmm::launch_ts_tn(A, lda, p, B, ldb, q, n, part, C, s);
+        hipError_t e = dense_mark();
+        if (e == hipSuccess) e = spmm::launch_ts_tn(A, lda, p, B, ldb, q, n, part, C, s);
+        if (e == hipSuccess) e = dense_mark();
+        dense_bytes += 4.0 * (double)n * (p + q);
         return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis product launch");
     }
     spmm_status_t nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta, float* Wo,
                      int64_t ldw) {
-        hipError_t e = spmm::launch_ts_nn(A, lda, p, C, q, alpha, beta, Wo, ldw, n, s);
+        hipError_t e = dense_mark();
+        if (e == hipSuccess) e = spmm::launch_ts_nn(A, lda, p, C, q, alpha, beta, Wo, ldw, n, s);
+        if (e == hipSuccess) e = dense_mark();
+        dense_bytes += 4.0 * (double)n * (p + (alpha != 0.0 ? 2 : 1) * q);
         return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis update launch");
     }
     spmm_status_t fill(float* X, int64_t ldx, int q) {
@@ -140,7 +174,9 @@ struct Solver {
     spmm_status_t product(const float* X, float* Y) {
         hipError_t e;
         if ((e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        spmm_status_t st = spmm_abi::run_device(H, X, b, ldv, SPMM_X_F32, nullptr, Y, b, s, false);
+        spmm_status_t st = H.place == SPMM_PLACE_DEVICE
+                               ? spmm_abi::run_device(H, X, b, ldv, SPMM_X_F32, nullptr, Y, b, s, false)
+                               : spmm_stream_run(h, X, b, ldv, SPMM_X_F32, nullptr, Y, b, s, copy);
         if (st != SPMM_OK) return st;
         if ((e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         if ((e = hipEventSynchronize(ev1)) != hipSuccess) return hip_fail(e, "SpMM");
@@ -259,6 +295,33 @@ struct Solver {
 
 }  // namespace
 
+extern "C" size_t spmm_dense_tn_workspace(int64_t n, int p, int q) {
+    (void)n;
+    if (p < 1 || q < 1) return 0;
+    return spmm::ts_partial_doubles() * sizeof(double);
+}
+
+extern "C" spmm_status_t spmm_dense_tn(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q,
+                                       int64_t n, double* C, void* work, size_t work_bytes, hipStream_t s) {
+    if (p < 1 || q < 1 || p > spmm::ts_max_width() || q > 16 || p * q > spmm::ts_max_outputs() || n < 0)
+        return fail(SPMM_EINVAL, "need 1 <= p <= " + std::to_string(spmm::ts_max_width()) + ", 1 <= q <= 16, p q <= " +
+                                     std::to_string(spmm::ts_max_outputs()) + ", n >= 0");
+    if (lda < p || ldb < q) return fail(SPMM_EINVAL, "lda must be >= p and ldb >= q");
+    if (!C || !work || (n > 0 && (!A || !B))) return fail(SPMM_EINVAL, "NULL argument");
+    if (work_bytes < spmm_dense_tn_workspace(n, p, q)) return fail(SPMM_EINVAL, "workspace too small");
+    hipError_t e = spmm::launch_ts_tn(A, lda, p, B, ldb, q, n, static_cast<double*>(work), C, s);
+    return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis product launch");
+}
+
+extern "C" spmm_status_t spmm_dense_nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha,
+                                       double beta, float* W, int64_t ldw, int64_t n, hipStream_t s) {
+    if (p < 1 || q < 1 || n < 0) return fail(SPMM_EINVAL, "need p >= 1, q >= 1, n >= 0");
+    if (lda < p || ldw < q) return fail(SPMM_EINVAL, "lda must be >= p and ldw >= q");
+    if (n > 0 && (!A || !C || !W)) return fail(SPMM_EINVAL, "NULL argument");
+    hipError_t e = spmm::launch_ts_nn(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
+    return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis update launch");
+}
+
 extern "C" spmm_status_t spmm_sym_eig_small(int n, const double* a, double* w, double* z) {
     if (n < 1 || n > 4096 || !a || !w || !z) return fail(SPMM_EINVAL, "need 1 <= n <= 4096 and non-NULL arrays");
     std::vector<double> A(a, a + (size_t)n * n), wv, zv;
@@ -281,7 +344,6 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
         if (!h || !o || !evals) return fail(SPMM_EINVAL, "NULL argument");
         spmm::Handle& H = h->H;
         if (H.n_rows != H.n_cols) return fail(SPMM_EINVAL, "the matrix must be square (and symmetric)");
-        if (H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "tiles are placed in host memory");
         const int64_t n = H.n_rows;
         const int nev = o->nev;
         const int b = o->block == 0 ? 4 : o->block;
@@ -294,9 +356,10 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
         int m = o->max_dim;
         if (m == 0) {
             // a wide basis: power-law spectra have clustered top eigenvalues,
-            // and restarting a narrow basis converges slowly
+            // and restarting a narrow basis converges slowly; a block method
+            // needs about 24 blocks for the same polynomial degree
             const int64_t cap = std::min<int64_t>({spmm::ts_max_outputs() / b, spmm::ts_max_width() - b, n - b});
-            m = (int)std::min<int64_t>(((std::max(6 * nev, nev + 4 * b) + b - 1) / b) * b, cap / b * b);
+            m = (int)std::min<int64_t>(((std::max({6 * nev, nev + 4 * b, 24 * b}) + b - 1) / b) * b, cap / b * b);
         }
         if (m % b != 0 || m < nev + b) return fail(SPMM_EINVAL, "max_dim must be a multiple of block and >= nev + block");
         if ((int64_t)m + b > n) return fail(SPMM_EINVAL, "max_dim + block exceeds the matrix order");
@@ -306,10 +369,30 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
         if (evecs && ldvec < nev) return fail(SPMM_EINVAL, "ldvec must be >= nev");
         spmm_status_t st = spmm_abi::prepare_device(H);
         if (st != SPMM_OK) return st;
+        hipError_t e;
+        // tiles in host memory: the solver runs on streams of its own (the
+        // products stream the tiles on a copy stream, as spmm_stream_run)
+        // after the work already queued on s
+        struct OwnStreams {
+            hipStream_t compute = nullptr, copy = nullptr;
+            ~OwnStreams() {
+                if (compute) (void)hipStreamSynchronize(compute);
+                if (copy) (void)hipStreamSynchronize(copy);
+                if (compute) (void)hipStreamDestroy(compute);
+                if (copy) (void)hipStreamDestroy(copy);
+            }
+        } own;
+        if (H.place != SPMM_PLACE_DEVICE) {
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "caller stream");
+            if ((e = hipStreamCreateWithFlags(&own.compute, hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipStreamCreateWithFlags(&own.copy, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreate");
+            s = own.compute;
+        }
 
         const int ldv = ((m + b + 3) / 4) * 4;
         spmm_abi::DevBufs bufs;
-        Solver S{H, s, n, b, m, ldv};
+        Solver S{h, H, s, own.copy, n, b, m, ldv};
         S.V[0] = bufs.get<float>((size_t)n * ldv);
         S.V[1] = bufs.get<float>((size_t)n * ldv);
         S.W = bufs.get<float>((size_t)n * b);
@@ -326,9 +409,9 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
                 (void)hipStreamSynchronize(S.s);
                 if (S.ev0) (void)hipEventDestroy(S.ev0);
                 if (S.ev1) (void)hipEventDestroy(S.ev1);
+                for (hipEvent_t e : S.dense_ev) (void)hipEventDestroy(e);
             }
         } cleanup{S};
-        hipError_t e;
         if ((e = hipEventCreate(&S.ev0)) != hipSuccess || (e = hipEventCreate(&S.ev1)) != hipSuccess)
             return hip_fail(e, "hipEventCreate");
 
@@ -433,6 +516,8 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
             if ((st = S.nn(Vc, ldv, m, S.dM, nev, 0.0, 1.0, evecs, ldvec)) != SPMM_OK) return st;
         }
         if ((st = S.sync("eigensolver")) != SPMM_OK) return st;
+        double dense_ms = 0.0;
+        if ((st = S.dense_ms(dense_ms)) != SPMM_OK) return st;
         if (info) {
             info->n_converged = n_conv;
             info->restarts = restarts;
@@ -442,6 +527,8 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
             info->max_dim = m;
             info->block = b;
+            info->dense_ms = dense_ms;
+            info->dense_bytes = S.dense_bytes;
         }
         if (n_conv < nev)
             return fail(SPMM_ENOTCONV, std::to_string(n_conv) + " of " + std::to_string(nev) +

@@ -69,9 +69,9 @@ def test_eigs_argument_checks_before_device():
     hr = pk.spmm_build_tiles(rp, col, n_cols=n + 7)
     assert _err(pk.spmm_eigs, hr, 2).status == pk.SPMM_EINVAL
     hr.close()
-    # tiles in host memory
+    # argument errors are reported before any device work for tiles in host memory too
     hs = pk.spmm_build_tiles(rp, col, place=pk.SPMM_PLACE_PINNED_HOST)
-    assert _err(pk.spmm_eigs, hs, 2).status == pk.SPMM_ESTATE
+    assert _err(pk.spmm_eigs, hs, 4, block=4, max_dim=6).status == pk.SPMM_EINVAL
     hs.close()
 
 

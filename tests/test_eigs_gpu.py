@@ -164,6 +164,23 @@ def test_not_converged_reports_current_pairs():
     assert torch.isfinite(V).all()
 
 
+@pytest.mark.parametrize("block", [1, 4])
+def test_semi_external_equals_in_hbm(block):
+    """Tiles in pinned host memory, streamed per product in small transfer
+    groups: the same kernels on the same work items, so the whole solve is
+    bit-identical to the in-HBM one."""
+    rp, col = _graph(12, 16, 2)
+    n = len(rp) - 1
+    hd = pk.spmm_build_tiles(rp, col)
+    hs = pk.spmm_build_tiles(rp, col, place=pk.SPMM_PLACE_PINNED_HOST, stream_kib=64, ring_depth=2)
+    a = _solve(hd, n, 8, block=block, seed=3)
+    b = _solve(hs, n, 8, block=block, seed=3)
+    hd.close()
+    hs.close()
+    assert a[2]["n_spmm"] == b[2]["n_spmm"] and a[2]["n_converged"] == 8
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[3], b[3])
+
+
 def test_sampled_residuals_scale_20():
     """A million-vertex graph: the oracle checks the residual on sampled rows
     (hub rows plus spread blocks), the orthonormality is checked in full."""
