@@ -221,9 +221,10 @@ struct Solver {
     // Dst (n x b, stride ldd) = Src (n x b, stride lds) G^{-1/2} for the Gram
     // matrix G of Src (symmetric inverse square root from G's eigenvectors):
     // one SVQB pass (Stathopoulos and Wu, SIAM J. Sci. Comput. 23(6), 2002).
-    // w, U: G's eigen-decomposition if already known, else empty.
+    // w, U: G's eigen-decomposition if already known, else empty.  sqrtG, if
+    // given, receives G^{1/2} (Src = Dst G^{1/2}).
     spmm_status_t svqb(const float* Src, int64_t lds, float* Dst, int64_t ldd, std::vector<double> w = {},
-                       std::vector<double> U = {}) {
+                       std::vector<double> U = {}, std::vector<double>* sqrtG = nullptr) {
         spmm_status_t st;
         if (w.empty()) {
             std::vector<double> G;
@@ -240,16 +241,26 @@ struct Solver {
                 for (int l = 0; l < b; ++l) v += U[(size_t)i * b + l] * U[(size_t)j * b + l] / std::sqrt(w[l]);
                 M[(size_t)i * b + j] = v;
             }
+        if (sqrtG) {
+            sqrtG->assign((size_t)b * b, 0.0);
+            for (int i = 0; i < b; ++i)
+                for (int j = 0; j < b; ++j) {
+                    double v = 0.0;
+                    for (int l = 0; l < b; ++l) v += U[(size_t)i * b + l] * U[(size_t)j * b + l] * std::sqrt(w[l]);
+                    (*sqrtG)[(size_t)i * b + j] = v;
+                }
+        }
         if ((st = put(dM, M.data(), M.size())) != SPMM_OK) return st;
         return nn(Src, lds, b, dM, b, 0.0, 1.0, Dst, ldd);
     }
 
     // Make the block W (n x b, stride b) orthogonal to the first nb columns
     // of Vc and orthonormal, writing it to Dst (stride ldv): W ~ Dst R.  coef
-    // receives Vb^T W (nb x b), R (b x b) is Dst^T W after the projection.
-    // Directions of W lost to cancellation are replaced by random vectors
-    // orthogonal to the basis (a breakdown of the Krylov space), with R
-    // computed explicitly so that the Krylov relation keeps holding.
+    // receives Vb^T W (nb x b), R (b x b) is Dst^T W after the projection
+    // (from the two Gram matrices when W has full rank).  Directions of W
+    // lost to cancellation are replaced by random vectors orthogonal to the
+    // basis (a breakdown of the Krylov space), with R = Dst^T W computed
+    // explicitly so that the Krylov relation keeps holding.
     spmm_status_t orthonormalise(const float* Vc, int nb, float* Dst, std::vector<double>& coef,
                                  std::vector<double>& R) {
         spmm_status_t st;
@@ -263,8 +274,9 @@ struct Solver {
         for (int l = 0; l < b; ++l)
             if (w[l] > kRankTol * scale2 && w[l] > 0.0) keep.push_back(l);
         const int r = (int)keep.size();
+        std::vector<double> s1, s2;
         if (r == b) {
-            if ((st = svqb(W, b, Z, b, w, U)) != SPMM_OK) return st;
+            if ((st = svqb(W, b, Z, b, w, U, &s1)) != SPMM_OK) return st;
         } else {
             // Z[:, 0:r] = W U_keep diag(1/sqrt(w_keep)), then random columns
             std::vector<double> M((size_t)b * std::max(r, 1), 0.0);
@@ -285,8 +297,19 @@ struct Solver {
             if (e != hipSuccess) return hip_fail(e, "basis block copy");
         }
         // second pass for orthogonality within the block
-        if ((st = svqb(Z, b, Dst, ldv)) != SPMM_OK) return st;
+        if ((st = svqb(Z, b, Dst, ldv, {}, {}, &s2)) != SPMM_OK) return st;
         R.resize((size_t)b * b);
+        if (r == b) {
+            // W = Z G1^{1/2} and Z = Dst G2^{1/2}, so R = G2^{1/2} G1^{1/2}:
+            // no pass over the new block
+            for (int i = 0; i < b; ++i)
+                for (int j = 0; j < b; ++j) {
+                    double v = 0.0;
+                    for (int l = 0; l < b; ++l) v += s2[(size_t)i * b + l] * s1[(size_t)l * b + j];
+                    R[(size_t)i * b + j] = v;
+                }
+            return SPMM_OK;
+        }
         if ((st = tn(Dst, ldv, b, W, b, b, dC)) != SPMM_OK) return st;
         if ((st = get(R.data(), dC, R.size())) != SPMM_OK) return st;
         return sync("block orthonormalisation");

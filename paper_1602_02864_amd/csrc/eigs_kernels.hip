@@ -16,72 +16,99 @@ namespace spmm {
 namespace {
 
 constexpr int kTsThreads = 256;
+constexpr int kTsWaves = kTsThreads / 64;
 constexpr int kTsMaxBlocks = 2048;  // row ranges of C = A^T B, one partial each
 constexpr int kTsMaxOut = 1024;     // p * q
 constexpr int kTsMaxP = 512;        // columns of A in C = A^T B
 constexpr int kTsMaxQ = 16;         // columns of B in C = A^T B
-constexpr int kNnCols = 32;         // columns of A staged in LDS per step of W += A C
+constexpr int kTnCols = 64;         // columns of A per blockIdx.y in C = A^T B
+constexpr int kTnU = 8;             // rows per lane per batch in C = A^T B
 
 // Row ranges for C = A^T B: a function of n only, so results are
 // reproducible for a given n.
 int tn_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kTsMaxBlocks, (n + 63) / 64)); }
 
-// part[(a * q + c) * nblk + blk] = sum over block blk's rows i of A[i][a] B[i][c],
-// for the columns a in [256 y, 256 y + pc) of blockIdx.y = y.  The block's
-// threads form G = 256 / pc groups of pc lanes; lane a of group g reads
-// A[i][a] for the rows i = r0 + g, r0 + g + G, ... (a group reads a row's
-// slice of A contiguously) and B[i][0..q) (one address per group), keeping q
-// FP64 sums; the groups are then added in order through LDS.
+__device__ inline int pow2_at_least(int x) {
+    int v = 1;
+    while (v < x) v <<= 1;
+    return v;
+}
+
+// part[(a * q + c) * nblk + blk] = sum over block blk's rows i of A[i][a] B[i][c]
+// for the columns a in [64 y, 64 y + pc) of blockIdx.y = y.  Each wavefront
+// owns batches of rows: its lanes form 64 / ncol row slots of ncol lanes
+// (ncol = pc rounded up to a power of two), lane (slot, a) reads A[i][a] for
+// U rows i of its slot, and the batch's rows of B are loaded once, coalesced,
+// into the wavefront's own LDS region and read from there (one address per
+// slot).  Loads use clamped, always-valid indices, so a batch's loads are all
+// in flight before its first FMA; invalid rows and columns contribute 0.
+// The lanes' FP64 sums are then added in a fixed order through LDS.
 template <int Q>
 __global__ __launch_bounds__(kTsThreads) void ts_tn_partial_kernel(const float* __restrict__ A, int64_t lda, int p,
                                                                    const float* __restrict__ B, int64_t ldb, int q,
                                                                    int64_t n, double* __restrict__ part) {
-    // rows per batch: all loads of a batch are issued before the first FMA;
-    // sums for c >= q repeat column q - 1 (a valid address, no branch) and
-    // are never written out
-    constexpr int U = Q <= 4 ? 8 : (Q <= 8 ? 4 : 2);
-    __shared__ double red[kTsThreads * Q];
+    __shared__ double smem[kTsThreads * Q];   // B batches during the sweep, then the lanes' sums
     const int nblk = gridDim.x;
-    const int a0 = blockIdx.y * kTsThreads;
-    const int pc = min(kTsThreads, p - a0);
-    const int G = kTsThreads / pc;
-    const int g = threadIdx.x / pc, a = threadIdx.x - g * pc;
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    float* sb = reinterpret_cast<float*>(smem) + wv * 64 * Q;   // this wavefront's B rows, 64 x Q floats
+    const int a0 = blockIdx.y * kTnCols;
+    const int pc = min(kTnCols, p - a0);
+    const int ncol = pow2_at_least(pc);
+    const int rs = 64 / ncol;                                     // row slots per wavefront
+    const int U = min(kTnU, 64 / rs);                             // rows per slot per batch
+    const int RB = rs * U;                                        // rows per batch (<= 64)
+    const int slot = lane / ncol, col = lane - (lane / ncol) * ncol;
+    const bool active = col < pc;
+    const float* ac = A + a0 + (active ? col : 0);
     const int64_t per = (n + nblk - 1) / nblk;
     const int64_t r0 = std::min<int64_t>(n, (int64_t)blockIdx.x * per);
     const int64_t r1 = std::min<int64_t>(n, r0 + per);
     double acc[Q];
 #pragma unroll
     for (int c = 0; c < Q; ++c) acc[c] = 0.0;
-    if (g < G) {
-        const float* ac = A + a0 + a;
-        int64_t i = r0 + g;
-        for (; i + (int64_t)(U - 1) * G < r1; i += (int64_t)U * G) {
-            float x[U], y[U][Q];
+    for (int64_t base = r0 + (int64_t)wv * RB; base < r1; base += (int64_t)kTsWaves * RB) {
+        const int nr = (int)std::min<int64_t>(RB, r1 - base);
+        float y[Q];   // B entries this lane stages: rows e / Q of the batch for e = lane + 64 j
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t r = i + (int64_t)u * G;
-                x[u] = ac[r * lda];
-#pragma unroll
-                for (int c = 0; c < Q; ++c) y[u][c] = B[r * ldb + (c < q ? c : q - 1)];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int c = 0; c < Q; ++c) acc[c] += (double)x[u] * (double)y[u][c];
+        for (int j = 0; j < Q; ++j) {
+            const int e = lane + 64 * j;
+            const int r = min(e / Q, nr - 1), c = min(e % Q, q - 1);
+            y[j] = B[(base + r) * ldb + c];
         }
-        for (; i < r1; i += G) {
-            const double xv = (double)ac[i * lda];
+        float x[kTnU];
 #pragma unroll
-            for (int c = 0; c < Q; ++c) acc[c] += xv * (double)B[i * ldb + (c < q ? c : q - 1)];
+        for (int u = 0; u < kTnU; ++u) {
+            const int r = min(slot + u * rs, nr - 1);
+            x[u] = ac[(base + r) * lda];
         }
+#pragma unroll
+        for (int j = 0; j < Q; ++j) sb[lane + 64 * j] = y[j];
+        // the wavefront's own LDS region: order its writes before its reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int u = 0; u < kTnU; ++u) {
+            const int r = slot + u * rs;
+            const double xv = (u < U && r < nr && active) ? (double)x[u] : 0.0;
+            const float* br = sb + min(r, nr - 1) * Q;
+#pragma unroll
+            for (int c = 0; c < Q; ++c) acc[c] += xv * (double)br[c];
+        }
+        // all lanes have read this batch before the next one overwrites it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < Q; ++c) red[threadIdx.x * Q + c] = acc[c];
+    for (int c = 0; c < Q; ++c) smem[threadIdx.x * Q + c] = acc[c];
     __syncthreads();
     for (int o = threadIdx.x; o < pc * q; o += kTsThreads) {
         const int aa = o / q, c = o - (o / q) * q;
         double s = 0.0;
-        for (int gg = 0; gg < G; ++gg) s += red[(gg * pc + aa) * Q + c];
+        for (int w = 0; w < kTsWaves; ++w)
+            for (int sl = 0; sl < rs; ++sl) s += smem[(w * 64 + sl * ncol + aa) * Q + c];
         part[((size_t)(a0 + aa) * q + c) * nblk + blockIdx.x] = s;
     }
 }
@@ -103,57 +130,134 @@ __global__ __launch_bounds__(kTsThreads) void ts_tn_final_kernel(const double* _
     if (threadIdx.x == 0) C[o] = red[0];
 }
 
-// W[i][c0 + c] = alpha W[i][c0 + c] + beta sum_a A[i][a] C[a][c0 + c] for the
-// output columns [c0, c0 + QC) of blockIdx.y: one thread per row (256 rows
-// per block).  A is staged through LDS 32 columns at a time with coalesced
-// loads (row stride 33 floats: the per-thread row reads hit distinct banks),
-// with the matching 32 rows of C (every thread reads the same entry: an LDS
-// broadcast).
-template <int QC>
+// W = alpha W + beta A C for q <= 16 output columns (QC >= q): one thread
+// per row, 256 rows per block.  A is staged through LDS CW columns at a
+// time with coalesced loads (row stride CW + 1 floats: the per-thread row
+// reads hit distinct banks), with the matching CW rows of C (every thread
+// reads the same entry: a broadcast).  The block's 256 x q results go back
+// through LDS so that W is read and written with consecutive lanes on
+// consecutive elements.
+template <int QC, int CW>
 __global__ __launch_bounds__(kTsThreads) void ts_nn_kernel(const float* __restrict__ A, int64_t lda, int p,
                                                            const double* __restrict__ C, int q, double alpha,
                                                            double beta, float* __restrict__ W, int64_t ldw,
                                                            int64_t n) {
-    __shared__ float sa[kTsThreads * (kNnCols + 1)];
-    __shared__ double sc[kNnCols * QC];
+    constexpr int kA = (kTsThreads * (CW + 1) + 1) / 2;     // doubles holding the A tile (floats)
+    constexpr int kOut = kTsThreads * QC;                    // doubles of the result tile
+    __shared__ double sbuf[kA > kOut ? kA : kOut];
+    __shared__ double sc[CW * QC];
+    float* sa = reinterpret_cast<float*>(sbuf);
     const int64_t row0 = (int64_t)blockIdx.x * kTsThreads;
-    const int c0 = blockIdx.y * QC;
-    const int qc = min(QC, q - c0);
+    const int rows = (int)std::min<int64_t>(kTsThreads, n - row0);
     double acc[QC];
 #pragma unroll
     for (int c = 0; c < QC; ++c) acc[c] = 0.0;
-    for (int a0 = 0; a0 < p; a0 += kNnCols) {
-        const int pw = min(kNnCols, p - a0);
-        // thread t loads column t % 32 of rows t / 32 + 8 j: all 32 loads in flight together
-        constexpr int kRowsPerPass = kTsThreads / kNnCols;
-        const int cc = threadIdx.x % kNnCols;
-        float v[kNnCols];
+    constexpr int kRowsPerPass = kTsThreads / CW;
+    const int cc = threadIdx.x % CW;
+    for (int a0 = 0; a0 < p; a0 += CW) {
+        const int pw = min(CW, p - a0);
+        // thread t loads column t % CW of rows t / CW + (256 / CW) j
+        float v[CW];
 #pragma unroll
-        for (int j = 0; j < kNnCols; ++j) {
-            const int64_t i = row0 + threadIdx.x / kNnCols + j * kRowsPerPass;
-            v[j] = (cc < pw && i < n) ? A[i * lda + a0 + cc] : 0.0f;
+        for (int j = 0; j < CW; ++j) {
+            const int r = min(threadIdx.x / CW + j * kRowsPerPass, rows - 1);
+            v[j] = A[(row0 + r) * lda + a0 + min(cc, pw - 1)];
         }
 #pragma unroll
-        for (int j = 0; j < kNnCols; ++j) sa[(threadIdx.x / kNnCols + j * kRowsPerPass) * (kNnCols + 1) + cc] = v[j];
-        // this slice of C (rows a0 .. a0 + pw), zero past q and past pw
-        for (int e = threadIdx.x; e < kNnCols * QC; e += kTsThreads) {
+        for (int j = 0; j < CW; ++j) sa[(threadIdx.x / CW + j * kRowsPerPass) * (CW + 1) + cc] = cc < pw ? v[j] : 0.0f;
+        for (int e = threadIdx.x; e < CW * QC; e += kTsThreads) {
             const int r = e / QC, c = e - (e / QC) * QC;
-            sc[e] = (r < pw && c < qc) ? C[(size_t)(a0 + r) * q + c0 + c] : 0.0;
+            sc[e] = (r < pw && c < q) ? C[(size_t)(a0 + r) * q + c] : 0.0;
         }
         __syncthreads();
         for (int a = 0; a < pw; ++a) {
-            const double x = (double)sa[threadIdx.x * (kNnCols + 1) + a];
+            const double x = (double)sa[threadIdx.x * (CW + 1) + a];
 #pragma unroll
             for (int c = 0; c < QC; ++c) acc[c] += x * sc[a * QC + c];
         }
         __syncthreads();
     }
-    const int64_t i = row0 + threadIdx.x;
-    if (i < n) {
-        float* w = W + i * ldw + c0;
+    double* so = sbuf;
 #pragma unroll
-        for (int c = 0; c < QC; ++c)
-            if (c < qc) w[c] = (float)((alpha != 0.0 ? alpha * (double)w[c] : 0.0) + beta * acc[c]);
+    for (int c = 0; c < QC; ++c) so[threadIdx.x * QC + c] = acc[c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * q; e += kTsThreads) {
+        const int r = e / q, c = e - (e / q) * q;
+        float* w = W + (row0 + r) * ldw + c;
+        const double old = alpha != 0.0 ? alpha * (double)*w : 0.0;
+        *w = (float)(old + beta * so[r * QC + c]);
+    }
+}
+
+// W = alpha W + beta A C for wide C (the restart and the Ritz vectors): a
+// 64-row x 64-column tile of W per block, 4 x 4 of it per thread, with
+// 32-column slices of A and the matching 32 x 64 slice of C staged in LDS.
+__global__ __launch_bounds__(kTsThreads) void ts_nn_wide_kernel(const float* __restrict__ A, int64_t lda, int p,
+                                                                const double* __restrict__ C, int q, double alpha,
+                                                                double beta, float* __restrict__ W, int64_t ldw,
+                                                                int64_t n) {
+    constexpr int TR = 64, TC = 64, KA = 32;
+    __shared__ float sa[TR * (KA + 1)];
+    __shared__ double sc[KA * TC];
+    const int64_t row0 = (int64_t)blockIdx.x * TR;
+    const int c0 = blockIdx.y * TC;
+    const int rows = (int)std::min<int64_t>(TR, n - row0);
+    const int cols = min(TC, q - c0);
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;    // rows 4 ty .. +3, columns 4 tx .. +3
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int a0 = 0; a0 < p; a0 += KA) {
+        const int pw = min(KA, p - a0);
+        float v[TR * KA / kTsThreads];
+#pragma unroll
+        for (int j = 0; j < TR * KA / kTsThreads; ++j) {
+            const int e = threadIdx.x + kTsThreads * j;
+            const int r = min(e / KA, rows - 1), k = min(e % KA, pw - 1);
+            v[j] = A[(row0 + r) * lda + a0 + k];
+        }
+        double u[KA * TC / kTsThreads];
+#pragma unroll
+        for (int j = 0; j < KA * TC / kTsThreads; ++j) {
+            const int e = threadIdx.x + kTsThreads * j;
+            const int k = min(e / TC, pw - 1), c = min(e % TC, cols - 1);
+            u[j] = C[(size_t)(a0 + k) * q + c0 + c];
+        }
+#pragma unroll
+        for (int j = 0; j < TR * KA / kTsThreads; ++j) {
+            const int e = threadIdx.x + kTsThreads * j;
+            sa[(e / KA) * (KA + 1) + e % KA] = (e % KA) < pw ? v[j] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < KA * TC / kTsThreads; ++j) sc[threadIdx.x + kTsThreads * j] = u[j];
+        __syncthreads();
+        for (int k = 0; k < pw; ++k) {
+            double xa[4], cb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xa[i] = (double)sa[(4 * ty + i) * (KA + 1) + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cb[j] = sc[k * TC + 4 * tx + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += xa[i] * cb[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * ty + i;
+        if (r >= rows) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * tx + j;
+            if (c >= cols) continue;
+            float* w = W + (row0 + r) * ldw + c0 + c;
+            const double old = alpha != 0.0 ? alpha * (double)*w : 0.0;
+            *w = (float)(old + beta * acc[i][j]);
+        }
     }
 }
 
@@ -192,7 +296,12 @@ hipError_t launch_ts_tn(const float* A, int64_t lda, int p, const float* B, int6
                         double* part, double* C, hipStream_t s) {
     if (p < 1 || q < 1 || p > kTsMaxP || q > kTsMaxQ || p * q > kTsMaxOut || n < 0) return hipErrorInvalidValue;
     const int nblk = tn_blocks(n);
-    const dim3 grid(nblk, (p + kTsThreads - 1) / kTsThreads);
+    if (n == 0) {
+        // no rows: C = 0 (one empty row range)
+        hipLaunchKernelGGL(ts_tn_final_kernel, dim3(p * q), dim3(kTsThreads), 0, s, part, 0, C);
+        return hipGetLastError();
+    }
+    const dim3 grid(nblk, (p + kTnCols - 1) / kTnCols);
     if (q == 1)
         hipLaunchKernelGGL(ts_tn_partial_kernel<1>, grid, dim3(kTsThreads), 0, s, A, lda, p, B, ldb, q, n, part);
     else if (q == 2)
@@ -207,24 +316,33 @@ hipError_t launch_ts_tn(const float* A, int64_t lda, int p, const float* B, int6
     return hipGetLastError();
 }
 
+template <int QC>
+static void launch_nn_q(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta,
+                        float* W, int64_t ldw, int64_t n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + kTsThreads - 1) / kTsThreads));
+    if (p <= 8)
+        hipLaunchKernelGGL((ts_nn_kernel<QC, 8>), grid, dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+    else
+        hipLaunchKernelGGL((ts_nn_kernel<QC, 32>), grid, dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+}
+
 hipError_t launch_ts_nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta,
                         float* W, int64_t ldw, int64_t n, hipStream_t s) {
     if (p < 1 || q < 1 || n < 0) return hipErrorInvalidValue;
     if (n == 0) return hipSuccess;
-    const unsigned gx = (unsigned)((n + kTsThreads - 1) / kTsThreads);
     if (q == 1)
-        hipLaunchKernelGGL(ts_nn_kernel<1>, dim3(gx, 1), dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+        launch_nn_q<1>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
     else if (q == 2)
-        hipLaunchKernelGGL(ts_nn_kernel<2>, dim3(gx, 1), dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+        launch_nn_q<2>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
     else if (q <= 4)
-        hipLaunchKernelGGL(ts_nn_kernel<4>, dim3(gx, 1), dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+        launch_nn_q<4>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
     else if (q <= 8)
-        hipLaunchKernelGGL(ts_nn_kernel<8>, dim3(gx, 1), dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+        launch_nn_q<8>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
     else if (q <= 16)
-        hipLaunchKernelGGL(ts_nn_kernel<16>, dim3(gx, 1), dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+        launch_nn_q<16>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
     else
-        hipLaunchKernelGGL(ts_nn_kernel<32>, dim3(gx, (q + 31) / 32), dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha,
-                           beta, W, ldw, n);
+        hipLaunchKernelGGL(ts_nn_wide_kernel, dim3((unsigned)((n + 63) / 64), (q + 63) / 64), dim3(kTsThreads), 0, s,
+                           A, lda, p, C, q, alpha, beta, W, ldw, n);
     return hipGetLastError();
 }
 
