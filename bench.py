@@ -823,6 +823,7 @@ def run_other_modes(args, modes) -> int:
                        "dense_s": round(info["dense_ms"] / 1e3, 3),
                        "dense_gbs": round(info["dense_bytes"] / (info["dense_ms"] * 1e-3) / 1e9, 1),
                        "host_s": round((info["total_ms"] - info["spmm_ms"] - info["dense_ms"]) / 1e3, 3),
+                       "reorth": f'{info["n_reorth"]}/{info["n_orth"]}',
                        "evals": [float(x) for x in evals],
                        "resid_est_max": float(resid.max()),
                        "sampled_resid_rel_max": float(r_sel.max()),

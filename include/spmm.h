@@ -523,14 +523,17 @@ typedef struct {
     double dense_ms;      /* device time of the dense basis kernels (events) */
     double dense_bytes;   /* their algorithmic HBM bytes: 4 n (p + q) for
                              C = A^T B, 4 n (p + 2q) for W += A C            */
+    int64_t n_orth;       /* blocks projected out of the basis ...          */
+    int64_t n_reorth;     /* ... and how many needed the second projection  */
 } spmm_eigs_info;
 
 /*
  * Eigenpairs of a symmetric A (handle built from a symmetric CSR; symmetry
  * is not checked) with the block Krylov-Schur method: an orthonormal basis
  * V (n x (m + b) FP32 in HBM) grows one block at a time (W = A V_j by
- * spmm_run, projected out of V twice in FP64 arithmetic, then made
- * orthonormal by two SVQB passes), T = V^T A V is kept on the host in FP64,
+ * spmm_run, projected out of V in FP64 arithmetic -- a second time where
+ * the first projection cancelled a column by more than 1/sqrt(2) -- then
+ * made orthonormal by two SVQB passes), T = V^T A V is kept on the host in FP64,
  * and after m columns the Ritz pairs of T (cyclic Jacobi) decide: stop when
  * the nev wanted ones have residual estimates <= tol |theta|, else keep the
  * best p ~ (m + nev) / 2 Ritz vectors and the residual block and expand

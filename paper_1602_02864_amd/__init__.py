@@ -94,7 +94,8 @@ class spmm_eigs_opts(ctypes.Structure):
 class spmm_eigs_info(ctypes.Structure):
     _fields_ = [("n_converged", ctypes.c_int32), ("restarts", ctypes.c_int32), ("n_spmm", ctypes.c_int64),
                 ("spmm_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("max_dim", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("dense_ms", ctypes.c_double), ("dense_bytes", ctypes.c_double)]
+                ("block", ctypes.c_int32), ("dense_ms", ctypes.c_double), ("dense_bytes", ctypes.c_double),
+                ("n_orth", ctypes.c_int64), ("n_reorth", ctypes.c_int64)]
 
 
 def load_library():

@@ -107,6 +107,7 @@ struct Solver {
     uint64_t seed;
     uint64_t n_fill = 0;
     int64_t n_spmm = 0;
+    int64_t n_first_pass = 0, n_second_pass = 0;   // block projections, and how many needed a second
     double spmm_ms = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // dense kernels: an event pair around each launch (read back at the end)
@@ -265,9 +266,38 @@ struct Solver {
                                  std::vector<double>& R) {
         spmm_status_t st;
         double scale2 = 0.0;
-        if (nb > 0 && (st = project_out(Vc, nb, W, b, b, coef, scale2)) != SPMM_OK) return st;
         std::vector<double> G, w, U;
-        if ((st = gram(W, b, b, G)) != SPMM_OK) return st;
+        if (nb > 0) {
+            // one projection, and a second one only where the first cancelled
+            // a column of W by more than a factor 1/sqrt(2) (Daniel, Gragg,
+            // Kaufman and Stewart, Math. Comp. 30, 1976): with FP64 sums the
+            // first pass leaves W orthogonal to V to within V's own
+            // orthogonality times that factor
+            std::vector<double> c1((size_t)nb * b);
+            if ((st = tn(Vc, ldv, nb, W, b, b, dC)) != SPMM_OK) return st;
+            if ((st = nn(Vc, ldv, nb, dC, b, 1.0, -1.0, W, b)) != SPMM_OK) return st;
+            if ((st = get(c1.data(), dC, c1.size())) != SPMM_OK) return st;
+            if ((st = gram(W, b, b, G)) != SPMM_OK) return st;
+            coef = c1;
+            bool again = false;
+            for (int c = 0; c < b; ++c) {
+                double w0 = G[(size_t)c * b + c];
+                for (int r = 0; r < nb; ++r) w0 += c1[(size_t)r * b + c] * c1[(size_t)r * b + c];
+                if (G[(size_t)c * b + c] < 0.5 * w0) again = true;
+            }
+            for (double v : c1) scale2 += v * v;
+            if (again) {
+                ++n_second_pass;
+                if ((st = tn(Vc, ldv, nb, W, b, b, dC)) != SPMM_OK) return st;
+                if ((st = nn(Vc, ldv, nb, dC, b, 1.0, -1.0, W, b)) != SPMM_OK) return st;
+                if ((st = get(c1.data(), dC, c1.size())) != SPMM_OK) return st;
+                if ((st = gram(W, b, b, G)) != SPMM_OK) return st;
+                for (size_t i = 0; i < c1.size(); ++i) coef[i] += c1[i];
+            }
+            ++n_first_pass;
+        } else if ((st = gram(W, b, b, G)) != SPMM_OK) {
+            return st;
+        }
         for (int i = 0; i < b; ++i) scale2 += G[(size_t)i * b + i];
         jacobi_eig(b, G, w, U);
         std::vector<int> keep;
@@ -552,6 +582,8 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
             info->block = b;
             info->dense_ms = dense_ms;
             info->dense_bytes = S.dense_bytes;
+            info->n_reorth = S.n_second_pass;
+            info->n_orth = S.n_first_pass;
         }
         if (n_conv < nev)
             return fail(SPMM_ENOTCONV, std::to_string(n_conv) + " of " + std::to_string(nev) +
