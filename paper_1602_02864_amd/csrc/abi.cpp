@@ -657,6 +657,7 @@ spmm_status_t spmm_nmf(spmm_handle_t hA, spmm_handle_t hAT, int rank, int iters,
         if (st == SPMM_OK && hAT != hA) st = prepare_device(AT);
         if (st != SPMM_OK) return st;
         DevBufs B;
+        B.sync_on(s);
         float* S = B.get<float>((size_t)std::max(n, m) * rank);
         double* part = B.get<double>((size_t)spmm::gram_blocks() * rank * rank);
         float* G = B.get<float>((size_t)rank * rank);

@@ -33,10 +33,20 @@ spmm_status_t launch_items_only(spmm::Handle& H, const void* X, int k, int64_t l
                                 const float* col_scale, float* Y, int64_t ldy, hipStream_t s,
                                 const int32_t* fexp);
 
-// Scoped device buffers for the drivers that need a workspace.
+// Scoped device buffers for the drivers that need a workspace.  With
+// sync_on(s), the stream the buffers are used on is synchronised before they
+// are freed, so an error return in the middle of queued work cannot free
+// memory that kernels still use.
 struct DevBufs {
     std::vector<void*> p;
+    hipStream_t stream = nullptr;
+    bool sync_first = false;
+    void sync_on(hipStream_t s) {
+        stream = s;
+        sync_first = true;
+    }
     ~DevBufs() {
+        if (sync_first && !p.empty()) (void)hipStreamSynchronize(stream);
         for (void* q : p) (void)hipFree(q);
     }
     template <typename T>

@@ -198,6 +198,7 @@ spmm_status_t collect(spmm::Handle& H, int k, int dt, const spmm_tune_opts* opts
         max_slabs = std::max(max_slabs, c);
     }
     DevBufs B;
+    B.sync_on(s);
     const size_t esz = (size_t)xbytes_of(dt);
     void* X = B.get<uint8_t>((size_t)std::max<int64_t>(H.n_cols, 1) * k * esz);
     float* Y = B.get<float>((size_t)max_slabs * H.h * k);
@@ -338,6 +339,7 @@ spmm_status_t spmm_mlp_grad(const float* params, const float* feat, const float*
     if (n < 0) return fail(SPMM_EINVAL, "n must be >= 0");
     if (!params || !grad || (n > 0 && (!feat || !target))) return fail(SPMM_EINVAL, "NULL argument");
     DevBufs B;
+    B.sync_on(s);
     const size_t r = (size_t)std::max<int64_t>(n, 1);
     spmm::MlpScratch w{};
     w.x = B.get<float>(r * SPMM_NUM_FEATURES);
