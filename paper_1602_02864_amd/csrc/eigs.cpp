@@ -404,7 +404,7 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
         if (o->which != SPMM_EIGS_LM && o->which != SPMM_EIGS_LA && o->which != SPMM_EIGS_SA)
             return fail(SPMM_EINVAL, "which must be SPMM_EIGS_LM, _LA or _SA");
         const double tol = o->tol == 0.0 ? 1e-5 : o->tol;
-        if (!(tol > 0.0) || o->max_restarts < 0) return fail(SPMM_EINVAL, "need tol >= 0 and max_restarts >= 0");
+        if (!(tol > 0.0) || o->max_restarts < 0) return fail(SPMM_EINVAL, "need tol > 0 (0 selects 1e-5) and max_restarts >= 0");
         const int max_restarts = o->max_restarts == 0 ? 500 : o->max_restarts;
         int m = o->max_dim;
         if (m == 0) {
