@@ -156,7 +156,7 @@ def main() -> int:
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="run a plain device copy of this many GiB first (counter calibration)")
     ap.add_argument("--mode", default="spmm",
-                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps | eigs | dense "
+                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps | eigs | dense | sbm "
                          "(comma-separated)")
     ap.add_argument("--stream-kib", type=int, default=0, help="streamed mode: bytes per transfer group")
     ap.add_argument("--ring-depth", type=int, default=0, help="streamed mode: device ring slots")
@@ -164,6 +164,7 @@ def main() -> int:
     ap.add_argument("--nev", type=int, default=8, help="eigs mode: eigenpairs wanted")
     ap.add_argument("--eig-tol", type=float, default=1e-5, help="eigs mode: relative residual tolerance")
     ap.add_argument("--no-sem", action="store_true", help="eigs mode: skip the semi-external runs")
+    ap.add_argument("--sbm-scale", type=int, default=24, help="sbm mode: log2 of the vertex count")
     args = ap.parse_args()
     modes = args.mode.split(",")
     if args.gpus == 1 and modes != ["spmm"]:
@@ -494,7 +495,7 @@ def run_other_modes(args, modes) -> int:
     ef = args.edge_factor if args.edge_factor is not None else (28.0 if big else 44.0)
     sym = big
     t0 = time.perf_counter()
-    if modes == ["dense"]:          # only the row count matters
+    if modes == ["dense"] or modes == ["sbm"]:     # no R-MAT graph needed
         rp, col = np.zeros(2, np.int64), np.zeros(0, np.int32)
         n, nnz = 1 << scale, 0
     else:
@@ -788,6 +789,59 @@ def run_other_modes(args, modes) -> int:
                 log(f"dense {res}")
                 del Wr
             del A, B, W, work
+            print(json.dumps(out), flush=True)
+        elif mode == "sbm":
+            # Section 5's stochastic-block-model study: streamed (semi-external)
+            # SpMV relative to in-HBM SpMV, clustered vs randomly ordered
+            # vertices, for several cluster counts and inside/outside ratios.
+            # Tiles keep the given column order (the in-degree relabelling
+            # would erase the clusters).
+            sn = 1 << args.sbm_scale
+            samples = sn * 32
+            link = pinned_h2d_gbs()
+            out = {"mode": "sbm", "metric": "in-HBM time / streamed time (SpMV and k = 16)", "n_gpus": 1,
+                   "data": "synthetic", "config": {"n": sn, "edge_samples": samples, "keep_order": True,
+                                                   "link_gbs": round(link, 1)}, "graphs": []}
+            copy = torch.cuda.Stream(dev)
+            for clusters in (64, 4096):
+                for p_in in (0.5, 0.9):
+                    for clustered in (True, False):
+                        g_rp, g_col = synth.sbm_csr(sn, clusters, samples, p_in, clustered=clustered,
+                                                    seed=synth.SEED_GRAPH, progress=log)
+                        hd = pk.spmm_build_tiles(g_rp, g_col, validate=False, keep_order=True)
+                        hs = pk.spmm_build_tiles(g_rp, g_col, validate=False, keep_order=True,
+                                                 place=pk.SPMM_PLACE_PINNED_HOST)
+                        res = {"clusters": clusters, "in_out": f"{p_in / (1 - p_in):g}:1",
+                               "p_in": p_in, "clustered": clustered, "nnz": int(g_col.shape[0]),
+                               "payload_gb": round(pk.spmm_get_stats(hs)["blob_bytes"] / 1e9, 3)}
+                        for k in (1, 16):
+                            X = torch.from_numpy(synth.uniform(sn, k, seed=synth.SEED_X)).to(dev)
+                            Yd = torch.empty((sn, k), device=dev)
+                            Ys = torch.empty((sn, k), device=dev)
+                            imk = kernel_ms(hd, lambda: pk.spmm_run(hd, X, Yd, stream=stream))
+                            torch.cuda.synchronize()
+                            t0 = time.perf_counter()
+                            for _ in range(3):
+                                pk.spmm_run(hd, X, Yd, stream=stream)
+                            torch.cuda.synchronize()
+                            im = (time.perf_counter() - t0) / 3 * 1e3
+                            pk.spmm_stream_run(hs, X, Ys, copy=copy)
+                            torch.cuda.synchronize()
+                            t0 = time.perf_counter()
+                            for _ in range(3):
+                                pk.spmm_stream_run(hs, X, Ys, copy=copy)
+                                torch.cuda.synchronize()
+                            sem = (time.perf_counter() - t0) / 3 * 1e3
+                            same = bool(torch.equal(Yd, Ys))
+                            res[f"k{k}"] = {"im_ms": round(im, 3), "im_kernel_ms": round(imk, 3),
+                                            "sem_ms": round(sem, 3),
+                                            "im_over_sem": round(im / sem, 4), "identical": same}
+                            del X, Yd, Ys
+                        out["graphs"].append(res)
+                        log(f"sbm {res}")
+                        hd.close()
+                        hs.close()
+                        del g_rp, g_col
             print(json.dumps(out), flush=True)
         elif mode == "eigs":
             # eight largest-magnitude eigenpairs of the undirected graph

@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs (R-MAT graphs, dense matrices, edge weights).
+"""Seeded synthetic inputs (R-MAT and stochastic-block-model graphs, dense
+matrices, edge weights).
 
 Shared by the oracle tests and the GPU path; holds none of the SpMM method's
 arithmetic.  The heavy lifting is in ``synth.c`` (OpenMP), loaded through
@@ -63,6 +64,13 @@ def _load():
         L.synth_draw.restype = u64
         L.synth_draws.argtypes = [u64, u64, i64, vp]
         L.synth_draws.restype = None
+        L.synth_sbm_begin.argtypes = [i64, i64, i64, ctypes.c_double, ctypes.c_int, u64, ctypes.c_int,
+                                      ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.synth_sbm_begin.restype = ctypes.c_int
+        L.synth_sbm_samples.argtypes = [i64, i64, i64, i64, ctypes.c_double, u64, vp, vp]
+        L.synth_sbm_samples.restype = None
+        L.synth_sbm_perm.argtypes = [i64, u64, vp]
+        L.synth_sbm_perm.restype = None
         _lib = L
     return _lib
 
@@ -97,6 +105,51 @@ def rmat_csr(scale: int, edge_factor: float, seed: int = SEED_GRAPH, symmetrize:
     if progress:
         progress(f"R-MAT scale {scale}: rows sorted and deduplicated, nnz {col.shape[0]}")
     return row_ptr, col
+
+
+def sbm_csr(n: int, clusters: int, edges: int, p_in: float, clustered: bool = True, seed: int = SEED_GRAPH,
+            symmetrize: bool = False, progress=None):
+    """Stochastic block model graph as CSR (row_ptr int64[n+1], col int32[nnz]).
+
+    Vertices form ``clusters`` equal contiguous ranges; each of ``edges``
+    samples takes a uniform source u and, with probability ``p_in``, a target
+    uniform in u's cluster, else a uniform target (so the expected fraction
+    of edges inside clusters is p_in + (1 - p_in) / clusters).  With
+    ``clustered=False`` every vertex id is replaced by ``sbm_perm(n, seed)``
+    (the same graph, randomly ordered).  Self-loops and duplicates removed,
+    columns sorted within rows.
+    """
+    L = _load()
+    h = ctypes.c_void_p()
+    nn = ctypes.c_int64()
+    nnz = ctypes.c_int64()
+    rc = L.synth_sbm_begin(n, clusters, edges, p_in, int(bool(clustered)), seed, int(bool(symmetrize)),
+                           ctypes.byref(h), ctypes.byref(nn), ctypes.byref(nnz))
+    if rc != 0:
+        raise ValueError("synth_sbm_begin failed (bad arguments or out of memory)")
+    if progress:
+        progress(f"SBM n={n} clusters={clusters} p_in={p_in} {'clustered' if clustered else 'unclustered'}: "
+                 f"{edges} samples bucketed")
+    row_ptr = np.empty(nn.value + 1, dtype=np.int64)
+    col = np.empty(max(nnz.value, 1), dtype=np.int32)[: nnz.value]
+    L.synth_rmat_finish(h, _ptr(row_ptr), _ptr(col) if nnz.value else _ptr(np.empty(1, np.int32)))
+    return row_ptr, col
+
+
+def sbm_samples(n: int, clusters: int, e0: int, count: int, p_in: float, seed: int = SEED_GRAPH):
+    """Raw SBM samples (u, v) in cluster order for sample ids [e0, e0+count)."""
+    L = _load()
+    u = np.empty(count, dtype=np.uint32)
+    v = np.empty(count, dtype=np.uint32)
+    L.synth_sbm_samples(n, clusters, e0, count, p_in, seed, _ptr(u), _ptr(v))
+    return u, v
+
+
+def sbm_perm(n: int, seed: int = SEED_GRAPH) -> np.ndarray:
+    """The vertex relabelling of an unclustered SBM graph (a permutation of 0..n-1)."""
+    perm = np.empty(n, dtype=np.uint32)
+    _load().synth_sbm_perm(n, seed, _ptr(perm))
+    return perm
 
 
 def rmat_samples(scale: int, e0: int, count: int, seed: int = SEED_GRAPH,

@@ -45,7 +45,8 @@ static inline uint64_t draw(uint64_t key, uint64_t ctr) {
 
 uint64_t synth_draw(uint64_t key, uint64_t ctr) { return draw(key, ctr); }
 
-enum { STREAM_RMAT = 1, STREAM_XUNIF = 2, STREAM_XINT = 3, STREAM_WEIGHT = 4 };
+enum { STREAM_RMAT = 1, STREAM_XUNIF = 2, STREAM_XINT = 3, STREAM_WEIGHT = 4, STREAM_SBM = 5, STREAM_PERM = 6 };
+enum { KIND_RMAT = 0, KIND_SBM = 1 };
 
 /* ---------------------------------------------------------------- R-MAT */
 
@@ -58,6 +59,10 @@ typedef struct {
     int64_t* off;     /* [n+1] bucket offsets                */
     uint32_t* cnt;    /* [n]   unique entries per row        */
     uint32_t* bucket; /* [off[n]] sorted/deduped per row     */
+    int kind;         /* KIND_RMAT or KIND_SBM               */
+    int64_t clusters; /* SBM: clusters [k n / c, (k+1) n / c) */
+    uint32_t p_in;    /* SBM: P(edge drawn inside) * 2^32    */
+    uint32_t* perm;   /* SBM: vertex relabelling, or NULL    */
 } synth_graph;
 
 static inline void rmat_sample(const synth_graph* g, uint64_t e, uint32_t* u, uint32_t* v) {
@@ -77,6 +82,33 @@ static inline void rmat_sample(const synth_graph* g, uint64_t e, uint32_t* u, ui
     }
     *u = r;
     *v = c;
+}
+
+/* Uniform integer in [0, m) from the high 32 bits of z (m < 2^32). */
+static inline uint32_t below(uint64_t z, uint64_t m) { return (uint32_t)(((z >> 32) * m) >> 32); }
+
+/* Stochastic block model sample e: u uniform; with probability p_in, v
+   uniform in u's cluster, else v uniform over all vertices; then both are
+   relabelled by perm when the graph is unclustered. */
+static inline void sbm_sample(const synth_graph* g, uint64_t e, uint32_t* u, uint32_t* v) {
+    const uint64_t n = (uint64_t)g->n, c = (uint64_t)g->clusters;
+    const uint64_t z0 = draw(g->key, 3 * e), z1 = draw(g->key, 3 * e + 1), z2 = draw(g->key, 3 * e + 2);
+    uint32_t a = below(z0, n), b;
+    if ((uint32_t)(z1 >> 32) < g->p_in) {
+        const uint64_t k = (uint64_t)a * c / n;                      /* a's cluster */
+        const uint64_t lo = k * n / c, hi = (k + 1) * n / c;
+        b = (uint32_t)(lo + below(z2, hi - lo));
+    } else {
+        b = below(z2, n);
+    }
+    if (g->perm) { a = g->perm[a]; b = g->perm[b]; }
+    *u = a;
+    *v = b;
+}
+
+static inline void graph_sample(const synth_graph* g, uint64_t e, uint32_t* u, uint32_t* v) {
+    if (g->kind == KIND_SBM) sbm_sample(g, e, u, v);
+    else rmat_sample(g, e, u, v);
 }
 
 static void sort_u32(uint32_t* a, int64_t n) {
@@ -122,28 +154,13 @@ static void exclusive_scan_u32_to_i64(const uint32_t* in, int64_t* out, int64_t 
     free(part);
 }
 
-/*
- * Generate an R-MAT graph: nsamples edge samples at the given scale.
- * On success *out holds the sorted, deduplicated adjacency lists; call
- * synth_rmat_finish to copy them into caller-owned CSR arrays.
- * Returns 0 on success, -1 on allocation failure.
- */
-int synth_rmat_begin(int scale, int64_t nsamples, double a, double b, double c,
-                     uint64_t seed, int symmetrize, synth_graph** out,
-                     int64_t* n_out, int64_t* nnz_out) {
-    if (scale < 1 || scale > 31 || nsamples < 0) return -1;
-    synth_graph* g = (synth_graph*)calloc(1, sizeof(synth_graph));
-    if (!g) return -1;
-    g->scale = scale;
-    g->n = (int64_t)1 << scale;
-    g->nsamples = nsamples;
-    g->symmetrize = symmetrize;
-    g->key = synth_stream_key(seed, STREAM_RMAT);
-    g->ta = (uint32_t)floor(a * 4294967296.0);
-    g->tab = (uint32_t)floor((a + b) * 4294967296.0);
-    g->tabc = (uint32_t)floor((a + b + c) * 4294967296.0);
-    const int64_t n = g->n;
-    g->cnt = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
+/* Draw the samples of g (n, nsamples, symmetrize and the generator fields
+   set), bucket them by row, sort and deduplicate each row.  Returns 0, or
+   -1 on allocation failure (g is then freed). */
+static int graph_build(synth_graph* g, synth_graph** out, int64_t* n_out, int64_t* nnz_out) {
+    const int64_t n = g->n, nsamples = g->nsamples;
+    const int symmetrize = g->symmetrize;
+    g->cnt = (uint32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
     g->off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
     if (!g->cnt || !g->off) goto fail;
 
@@ -151,7 +168,7 @@ int synth_rmat_begin(int scale, int64_t nsamples, double a, double b, double c,
     #pragma omp parallel for schedule(static, 65536)
     for (int64_t e = 0; e < nsamples; ++e) {
         uint32_t u, v;
-        rmat_sample(g, (uint64_t)e, &u, &v);
+        graph_sample(g, (uint64_t)e, &u, &v);
         if (u == v) continue;
         __atomic_fetch_add(&g->cnt[u], 1u, __ATOMIC_RELAXED);
         if (symmetrize) __atomic_fetch_add(&g->cnt[v], 1u, __ATOMIC_RELAXED);
@@ -165,7 +182,7 @@ int synth_rmat_begin(int scale, int64_t nsamples, double a, double b, double c,
     #pragma omp parallel for schedule(static, 65536)
     for (int64_t e = 0; e < nsamples; ++e) {
         uint32_t u, v;
-        rmat_sample(g, (uint64_t)e, &u, &v);
+        graph_sample(g, (uint64_t)e, &u, &v);
         if (u == v) continue;
         uint32_t p = __atomic_fetch_add(&g->cnt[u], 1u, __ATOMIC_RELAXED);
         g->bucket[g->off[u] + p] = v;
@@ -195,8 +212,86 @@ int synth_rmat_begin(int scale, int64_t nsamples, double a, double b, double c,
     *nnz_out = nnz;
     return 0;
 fail:
-    free(g->cnt); free(g->off); free(g->bucket); free(g);
+    free(g->cnt); free(g->off); free(g->bucket); free(g->perm); free(g);
     return -1;
+}
+
+/*
+ * Generate an R-MAT graph: nsamples edge samples at the given scale.
+ * On success *out holds the sorted, deduplicated adjacency lists; call
+ * synth_rmat_finish to copy them into caller-owned CSR arrays.
+ * Returns 0 on success, -1 on allocation failure.
+ */
+int synth_rmat_begin(int scale, int64_t nsamples, double a, double b, double c,
+                     uint64_t seed, int symmetrize, synth_graph** out,
+                     int64_t* n_out, int64_t* nnz_out) {
+    if (scale < 1 || scale > 31 || nsamples < 0) return -1;
+    synth_graph* g = (synth_graph*)calloc(1, sizeof(synth_graph));
+    if (!g) return -1;
+    g->kind = KIND_RMAT;
+    g->scale = scale;
+    g->n = (int64_t)1 << scale;
+    g->nsamples = nsamples;
+    g->symmetrize = symmetrize;
+    g->key = synth_stream_key(seed, STREAM_RMAT);
+    g->ta = (uint32_t)floor(a * 4294967296.0);
+    g->tab = (uint32_t)floor((a + b) * 4294967296.0);
+    g->tabc = (uint32_t)floor((a + b + c) * 4294967296.0);
+    return graph_build(g, out, n_out, nnz_out);
+}
+
+/* Vertex relabelling of an unclustered SBM graph: a Fisher-Yates shuffle of
+   0..n-1 driven by the PERM stream of seed. */
+void synth_sbm_perm(int64_t n, uint64_t seed, uint32_t* perm) {
+    const uint64_t key = synth_stream_key(seed, STREAM_PERM);
+    for (int64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    for (int64_t i = n - 1; i > 0; --i) {
+        const int64_t j = (int64_t)below(draw(key, (uint64_t)i), (uint64_t)(i + 1));
+        uint32_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
+    }
+}
+
+/*
+ * Generate a stochastic block model graph: n vertices in `clusters` equal
+ * contiguous ranges, nsamples edge samples, each drawn inside its source's
+ * cluster with probability p_in, else uniformly; with clustered = 0 the
+ * vertices are relabelled by synth_sbm_perm(n, seed).  Self-loops and
+ * duplicates are removed.  Same contract as synth_rmat_begin.
+ */
+int synth_sbm_begin(int64_t n, int64_t clusters, int64_t nsamples, double p_in, int clustered, uint64_t seed,
+                    int symmetrize, synth_graph** out, int64_t* n_out, int64_t* nnz_out) {
+    if (n < 1 || n >= ((int64_t)1 << 31) || clusters < 1 || clusters > n || nsamples < 0 ||
+        !(p_in >= 0.0 && p_in <= 1.0))
+        return -1;
+    synth_graph* g = (synth_graph*)calloc(1, sizeof(synth_graph));
+    if (!g) return -1;
+    g->kind = KIND_SBM;
+    g->n = n;
+    g->nsamples = nsamples;
+    g->symmetrize = symmetrize;
+    g->clusters = clusters;
+    g->p_in = p_in >= 1.0 ? 0xFFFFFFFFu : (uint32_t)floor(p_in * 4294967296.0);
+    g->key = synth_stream_key(seed, STREAM_SBM);
+    if (!clustered) {
+        g->perm = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+        if (!g->perm) { free(g); return -1; }
+        synth_sbm_perm(n, seed, g->perm);
+    }
+    return graph_build(g, out, n_out, nnz_out);
+}
+
+/* Raw SBM samples (before self-loop removal and dedup), for generator tests. */
+void synth_sbm_samples(int64_t n, int64_t clusters, int64_t e0, int64_t count, double p_in, uint64_t seed,
+                       uint32_t* u, uint32_t* v) {
+    synth_graph g;
+    memset(&g, 0, sizeof g);
+    g.kind = KIND_SBM;
+    g.n = n;
+    g.clusters = clusters;
+    g.p_in = p_in >= 1.0 ? 0xFFFFFFFFu : (uint32_t)floor(p_in * 4294967296.0);
+    g.key = synth_stream_key(seed, STREAM_SBM);
+    #pragma omp parallel for schedule(static, 65536)
+    for (int64_t i = 0; i < count; ++i) sbm_sample(&g, (uint64_t)(e0 + i), &u[i], &v[i]);
 }
 
 /* Copy the graph into caller-owned row_ptr[n+1] / col[nnz] and free it. */
@@ -206,12 +301,12 @@ void synth_rmat_finish(synth_graph* g, int64_t* row_ptr, int32_t* col) {
     #pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t u = 0; u < n; ++u)
         memcpy(col + row_ptr[u], g->bucket + g->off[u], sizeof(uint32_t) * g->cnt[u]);
-    free(g->cnt); free(g->off); free(g->bucket); free(g);
+    free(g->cnt); free(g->off); free(g->bucket); free(g->perm); free(g);
 }
 
 void synth_rmat_free(synth_graph* g) {
     if (!g) return;
-    free(g->cnt); free(g->off); free(g->bucket); free(g);
+    free(g->cnt); free(g->off); free(g->bucket); free(g->perm); free(g);
 }
 
 /* Raw samples (before self-loop removal and dedup), for generator tests. */

@@ -92,3 +92,53 @@ def test_lognormal_weights_symmetric():
     assert all(d[(c, r)] == w for (r, c), w in d.items())
     z = np.log(val.astype(np.float64))
     assert abs(z.mean()) < 0.05 and abs(z.std() - 1) < 0.05
+
+
+# ---------------------------------------------------------------- SBM
+
+def _cluster(x, n, c):
+    return (x.astype(np.int64) * c) // n
+
+
+def test_sbm_samples_follow_the_model():
+    """Sources uniform; the fraction of targets in the source's cluster is
+    p_in + (1 - p_in) / c (within 5 standard errors); inside targets never
+    leave the cluster."""
+    n, c, p_in, m = 1 << 16, 64, 0.7, 1 << 20
+    u, v = synth.sbm_samples(n, c, 0, m, p_in, seed=3)
+    assert u.max() < n and v.max() < n
+    inside = _cluster(u, n, c) == _cluster(v, n, c)
+    p = p_in + (1 - p_in) / c
+    assert abs(inside.mean() - p) < 5 * np.sqrt(p * (1 - p) / m)
+    counts = np.bincount(_cluster(u, n, c), minlength=c)
+    assert abs(counts.mean() - m / c) < 1e-9 and counts.std() < 5 * np.sqrt(m / c)
+    # p_in = 1: every target inside; p_in = 0: inside only by chance
+    u1, v1 = synth.sbm_samples(n, c, 0, 1 << 16, 1.0, seed=3)
+    assert np.all(_cluster(u1, n, c) == _cluster(v1, n, c))
+    u0, v0 = synth.sbm_samples(n, c, 0, 1 << 16, 0.0, seed=3)
+    assert (_cluster(u0, n, c) == _cluster(v0, n, c)).mean() < 3.0 / c
+
+
+def test_sbm_csr_is_the_cleaned_samples_and_unclustered_is_a_relabelling():
+    n, c, p_in, m = 5000, 7, 0.6, 60000          # n not a multiple of c: ragged clusters
+    rp, col = synth.sbm_csr(n, c, m, p_in, clustered=True, seed=4)
+    u, v = synth.sbm_samples(n, c, 0, m, p_in, seed=4)
+    keep = u != v
+    ref = np.unique(u[keep].astype(np.int64) * n + v[keep])
+    got = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp)) * n + col
+    assert np.array_equal(got, ref)             # sorted rows, no duplicates, no self-loops
+    rp2, col2 = synth.sbm_csr(n, c, m, p_in, clustered=False, seed=4)
+    perm = synth.sbm_perm(n, seed=4).astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    relab = np.unique(perm[got // n] * n + perm[got % n])
+    got2 = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp2)) * n + col2
+    assert np.array_equal(got2, relab)
+    again = synth.sbm_csr(n, c, m, p_in, clustered=False, seed=4)
+    assert np.array_equal(again[0], rp2) and np.array_equal(again[1], col2)
+
+
+def test_sbm_rejects_bad_arguments():
+    import pytest
+    for args in ((0, 1, 10, 0.5), (10, 0, 10, 0.5), (10, 11, 10, 0.5), (10, 2, 10, 1.5)):
+        with pytest.raises(ValueError):
+            synth.sbm_csr(*args)
