@@ -127,3 +127,22 @@ def test_back_to_back_streamed_calls_identical():
         assert torch.equal(Y, ref)
     hd.close()
     hs.close()
+
+
+@pytest.mark.parametrize("clustered", [True, False])
+def test_sbm_graphs_exact_in_hbm_and_streamed(clustered):
+    """Stochastic-block-model inputs of the clustering study, with the given
+    column order kept and with the default relabelling: integer X exact
+    against the oracle, streamed Y identical to in-HBM Y."""
+    rp, col = synth.sbm_csr(1 << 14, 64, 1 << 19, 0.9, clustered=clustered, seed=6)
+    n = rp.shape[0] - 1
+    X = synth.int07(n, 4, seed=7)
+    ref = oracle.spmm(rp, col, None, X)
+    for keep in (True, False):
+        hd = pk.spmm_build_tiles(rp, col, keep_order=keep)
+        hs = pk.spmm_build_tiles(rp, col, keep_order=keep, place=pk.SPMM_PLACE_PINNED_HOST, stream_kib=64)
+        Yd = _dev_y(hd, X)
+        assert np.array_equal(Yd.astype(np.float64), ref), keep
+        assert np.array_equal(_stream_y(hs, X), Yd), keep
+        hd.close()
+        hs.close()
