@@ -160,7 +160,7 @@ def main() -> int:
                          "(comma-separated)")
     ap.add_argument("--stream-kib", type=int, default=0, help="streamed mode: bytes per transfer group")
     ap.add_argument("--ring-depth", type=int, default=0, help="streamed mode: device ring slots")
-    ap.add_argument("--eig-blocks", default="1,2,4,8", help="eigs mode: block sizes")
+    ap.add_argument("--eig-blocks", default="1,2,4,8,16", help="eigs mode: block sizes")
     ap.add_argument("--nev", type=int, default=8, help="eigs mode: eigenpairs wanted")
     ap.add_argument("--eig-tol", type=float, default=1e-5, help="eigs mode: relative residual tolerance")
     ap.add_argument("--no-sem", action="store_true", help="eigs mode: skip the semi-external runs")

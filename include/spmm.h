@@ -500,10 +500,11 @@ typedef struct {
     int32_t nev;          /* eigenpairs wanted, >= 1                                   */
     int32_t block;        /* block size b (vectors per SpMM), 1..16; 0 -> 4            */
     int32_t max_dim;      /* basis columns m before a restart: a multiple of b with
-                             m >= nev + b, m + b <= n, m * b <= 1024 and
+                             m >= nev + b, m + b <= n, m * b <= 2048 and
                              m + b <= 512;
-                             0 -> the smallest multiple of b >= max(6 nev, nev + 4b,
-                             24 b), lowered to the limits                          */
+                             0 -> the smallest multiple of b >= min(max(6 nev,
+                             nev + 4b, 24 b), max(128, 8 nev + 4b)), lowered to
+                             the limits                                            */
     int32_t which;        /* SPMM_EIGS_LM / _LA / _SA                                  */
     int32_t max_restarts; /* 0 -> 500                                                  */
     int32_t reserved;     /* 0                                                         */
@@ -553,7 +554,7 @@ typedef struct {
  *            (absolute if theta = 0); or NULL.
  *   info   : or NULL.
  * Device workspace: two n x round_up(m + b, 4) and two n x b FP32 buffers
- * plus 16 MiB, allocated per call (and the handle's ring, for tiles in host
+ * plus 32 MiB, allocated per call (and the handle's ring, for tiles in host
  * memory).  Synchronous (several host
  * round trips per block).  Errors: SPMM_EINVAL, SPMM_ENOMEM, SPMM_EHIP,
  * SPMM_ENOTCONV (max_restarts reached:
@@ -569,7 +570,7 @@ spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* opts, double* eva
  * of n rows (Section 4.2 notes that an eigensolver adds many dense matrix
  * operations to the SpMMs):
  *   spmm_dense_tn : C = A^T B.  A n x p (stride lda >= p), B n x q (stride
- *                   ldb >= q), 1 <= p <= 512, 1 <= q <= 16, p q <= 1024.
+ *                   ldb >= q), 1 <= p <= 512, 1 <= q <= 16, p q <= 2048.
  *                   C: device double p x q, row-major.  Products and sums
  *                   in FP64, summed in an order fixed by n alone (the same
  *                   bits for the same inputs).  work: device scratch of at

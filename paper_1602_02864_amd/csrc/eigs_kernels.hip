@@ -1,6 +1,6 @@
 // Dense kernels of the block Krylov-Schur eigensolver.  The basis V is a
 // tall, narrow FP32 matrix (n rows, at most a few hundred columns, row-major):
-//   ts_tn   C = A^T B            (A n x p, p <= 512, B n x q, q <= 16, p q <= 1024;
+//   ts_tn   C = A^T B            (A n x p, p <= 512, B n x q, q <= 16, p q <= 2048;
 //                                 C p x q FP64, row-major)
 //   ts_nn   W = alpha W + beta A C   (C p x q FP64; W must not alias A)
 //   fill_uniform  X[i][c] uniform in [-1/2, 1/2) from a counter-based hash.
@@ -18,7 +18,7 @@ namespace {
 constexpr int kTsThreads = 256;
 constexpr int kTsWaves = kTsThreads / 64;
 constexpr int kTsMaxBlocks = 2048;  // row ranges of C = A^T B, one partial each
-constexpr int kTsMaxOut = 1024;     // p * q
+constexpr int kTsMaxOut = 2048;     // p * q
 constexpr int kTsMaxP = 512;        // columns of A in C = A^T B
 constexpr int kTsMaxQ = 16;         // columns of B in C = A^T B
 constexpr int kTnCols = 64;         // columns of A per blockIdx.y in C = A^T B

@@ -19,7 +19,8 @@ def _dev(a):
 
 @pytest.mark.parametrize("n,p,q,lda,ldb", [(0, 3, 2, 3, 2), (1, 1, 1, 1, 1), (1000, 5, 3, 7, 4),
                                             (70001, 36, 2, 52, 2), (9000, 300, 3, 301, 3),
-                                            (12345, 64, 16, 64, 16), (5000, 512, 2, 520, 2)])
+                                            (12345, 64, 16, 64, 16), (5000, 512, 2, 520, 2),
+                                            (3000, 128, 16, 130, 16)])
 def test_tn_matches_fp64(n, p, q, lda, ldb):
     import torch
     A = synth.uniform(n, lda, seed=1) - 0.5

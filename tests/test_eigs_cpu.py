@@ -55,7 +55,7 @@ def test_eigs_argument_checks_before_device():
     n = len(rp) - 1
     h = pk.spmm_build_tiles(rp, col)
     for kw in (dict(nev=0), dict(nev=4, block=17), dict(nev=4, which="XX"), dict(nev=4, max_dim=10),
-               dict(nev=8, block=4, max_dim=8), dict(nev=4, block=16, max_dim=80), dict(nev=4, tol=-1.0),
+               dict(nev=8, block=4, max_dim=8), dict(nev=4, block=16, max_dim=144), dict(nev=4, tol=-1.0),
                dict(nev=4, max_restarts=-1), dict(nev=4, block=4, max_dim=n)):
         kw = dict(kw)
         nev = kw.pop("nev")

@@ -55,7 +55,7 @@ def _check_pairs(rp, col, val, evals, V, tol, lam1):
     return r
 
 
-@pytest.mark.parametrize("block", [1, 2, 4, 8])
+@pytest.mark.parametrize("block", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("graph", [(10, 8, 1), (12, 16, 2)])
 def test_largest_magnitude_matches_oracle(graph, block):
     rp, col = _graph(*graph)
