@@ -553,7 +553,8 @@ typedef struct {
  *   resid  : host double[nev], residual estimates ||A y - theta y|| / |theta|
  *            (absolute if theta = 0); or NULL.
  *   info   : or NULL.
- * Device workspace: two n x round_up(m + b, 4) and two n x b FP32 buffers
+ * Device workspace: two bases of n x (m + b) FP32 (stored as m / b + 1
+ * blocks of b columns, each n x b contiguous) and two n x b FP32 buffers
  * plus 32 MiB, allocated per call (and the handle's ring, for tiles in host
  * memory).  Synchronous (several host
  * round trips per block).  Errors: SPMM_EINVAL, SPMM_ENOMEM, SPMM_EHIP,

@@ -97,7 +97,8 @@ struct Solver {
     hipStream_t s;
     hipStream_t copy = nullptr;  // tiles in host memory: the stream of the tile copies
     int64_t n;
-    int b, m, ldv;
+    int b, m;
+    spmm::ColLayout VL;   // the basis: blocks of b columns, each n x b contiguous
     float* V[2];
     float* W;
     float* Z;    // n x b scratch block
@@ -151,17 +152,17 @@ struct Solver {
         // the host vector may change right after the call returns
         return sync("copy to device");
     }
-    spmm_status_t tn(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q, double* C) {
+    spmm_status_t tn(const float* A, spmm::ColLayout LA, int p, const float* B, int64_t ldb, int q, double* C) {
         hipError_t e = dense_mark();
-        if (e == hipSuccess) e = spmm::launch_ts_tn(A, lda, p, B, ldb, q, n, part, C, s);
+        if (e == hipSuccess) e = spmm::launch_ts_tn(A, LA, p, B, ldb, q, n, part, C, s);
         if (e == hipSuccess) e = dense_mark();
         dense_bytes += 4.0 * (double)n * (p + q);
         return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis product launch");
     }
-    spmm_status_t nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta, float* Wo,
-                     int64_t ldw) {
+    spmm_status_t nn(const float* A, spmm::ColLayout LA, int p, const double* C, int q, double alpha, double beta,
+                     float* Wo, spmm::ColLayout LW) {
         hipError_t e = dense_mark();
-        if (e == hipSuccess) e = spmm::launch_ts_nn(A, lda, p, C, q, alpha, beta, Wo, ldw, n, s);
+        if (e == hipSuccess) e = spmm::launch_ts_nn(A, LA, p, C, q, alpha, beta, Wo, LW, n, s);
         if (e == hipSuccess) e = dense_mark();
         dense_bytes += 4.0 * (double)n * (p + (alpha != 0.0 ? 2 : 1) * q);
         return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis update launch");
@@ -176,8 +177,8 @@ struct Solver {
         hipError_t e;
         if ((e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         spmm_status_t st = H.place == SPMM_PLACE_DEVICE
-                               ? spmm_abi::run_device(H, X, b, ldv, SPMM_X_F32, nullptr, Y, b, s, false)
-                               : spmm_stream_run(h, X, b, ldv, SPMM_X_F32, nullptr, Y, b, s, copy);
+                               ? spmm_abi::run_device(H, X, b, b, SPMM_X_F32, nullptr, Y, b, s, false)
+                               : spmm_stream_run(h, X, b, b, SPMM_X_F32, nullptr, Y, b, s, copy);
         if (st != SPMM_OK) return st;
         if ((e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         if ((e = hipEventSynchronize(ev1)) != hipSuccess) return hip_fail(e, "SpMM");
@@ -198,8 +199,8 @@ struct Solver {
         std::vector<double> c((size_t)nb * q);
         spmm_status_t st;
         for (int pass = 0; pass < 2; ++pass) {
-            if ((st = tn(Vc, ldv, nb, X, ldx, q, dC)) != SPMM_OK) return st;
-            if ((st = nn(Vc, ldv, nb, dC, q, 1.0, -1.0, X, ldx)) != SPMM_OK) return st;
+            if ((st = tn(Vc, VL, nb, X, ldx, q, dC)) != SPMM_OK) return st;
+            if ((st = nn(Vc, VL, nb, dC, q, 1.0, -1.0, X, spmm::row_major(ldx))) != SPMM_OK) return st;
             if ((st = get(c.data(), dC, c.size())) != SPMM_OK) return st;
             if ((st = sync("projection")) != SPMM_OK) return st;
             for (size_t i = 0; i < c.size(); ++i) {
@@ -213,7 +214,7 @@ struct Solver {
     // Gram matrix G = X^T X (q x q) of a device block, on the host.
     spmm_status_t gram(const float* X, int64_t ldx, int q, std::vector<double>& G) {
         G.resize((size_t)q * q);
-        spmm_status_t st = tn(X, ldx, q, X, ldx, q, dC);
+        spmm_status_t st = tn(X, spmm::row_major(ldx), q, X, ldx, q, dC);
         if (st == SPMM_OK) st = get(G.data(), dC, G.size());
         if (st == SPMM_OK) st = sync("Gram matrix");
         return st;
@@ -252,11 +253,11 @@ struct Solver {
                 }
         }
         if ((st = put(dM, M.data(), M.size())) != SPMM_OK) return st;
-        return nn(Src, lds, b, dM, b, 0.0, 1.0, Dst, ldd);
+        return nn(Src, spmm::row_major(lds), b, dM, b, 0.0, 1.0, Dst, spmm::row_major(ldd));
     }
 
     // Make the block W (n x b, stride b) orthogonal to the first nb columns
-    // of Vc and orthonormal, writing it to Dst (stride ldv): W ~ Dst R.  coef
+    // of Vc and orthonormal, writing it to the basis block Dst: W ~ Dst R.  coef
     // receives Vb^T W (nb x b), R (b x b) is Dst^T W after the projection
     // (from the two Gram matrices when W has full rank).  Directions of W
     // lost to cancellation are replaced by random vectors orthogonal to the
@@ -274,8 +275,8 @@ struct Solver {
             // first pass leaves W orthogonal to V to within V's own
             // orthogonality times that factor
             std::vector<double> c1((size_t)nb * b);
-            if ((st = tn(Vc, ldv, nb, W, b, b, dC)) != SPMM_OK) return st;
-            if ((st = nn(Vc, ldv, nb, dC, b, 1.0, -1.0, W, b)) != SPMM_OK) return st;
+            if ((st = tn(Vc, VL, nb, W, b, b, dC)) != SPMM_OK) return st;
+            if ((st = nn(Vc, VL, nb, dC, b, 1.0, -1.0, W, spmm::row_major(b))) != SPMM_OK) return st;
             if ((st = get(c1.data(), dC, c1.size())) != SPMM_OK) return st;
             if ((st = gram(W, b, b, G)) != SPMM_OK) return st;
             coef = c1;
@@ -288,8 +289,8 @@ struct Solver {
             for (double v : c1) scale2 += v * v;
             if (again) {
                 ++n_second_pass;
-                if ((st = tn(Vc, ldv, nb, W, b, b, dC)) != SPMM_OK) return st;
-                if ((st = nn(Vc, ldv, nb, dC, b, 1.0, -1.0, W, b)) != SPMM_OK) return st;
+                if ((st = tn(Vc, VL, nb, W, b, b, dC)) != SPMM_OK) return st;
+                if ((st = nn(Vc, VL, nb, dC, b, 1.0, -1.0, W, spmm::row_major(b))) != SPMM_OK) return st;
                 if ((st = get(c1.data(), dC, c1.size())) != SPMM_OK) return st;
                 if ((st = gram(W, b, b, G)) != SPMM_OK) return st;
                 for (size_t i = 0; i < c1.size(); ++i) coef[i] += c1[i];
@@ -315,19 +316,19 @@ struct Solver {
                     M[(size_t)i * r + j] = U[(size_t)i * b + keep[j]] / std::sqrt(w[keep[j]]);
             if (r > 0) {
                 if ((st = put(dM, M.data(), (size_t)b * r)) != SPMM_OK) return st;
-                if ((st = nn(W, b, b, dM, r, 0.0, 1.0, Z, b)) != SPMM_OK) return st;
+                if ((st = nn(W, spmm::row_major(b), b, dM, r, 0.0, 1.0, Z, spmm::row_major(b))) != SPMM_OK)
+                    return st;
             }
             if ((st = fill(Z + r, b, b - r)) != SPMM_OK) return st;
             std::vector<double> unused;
             double unused2;
             if (nb > 0 && (st = project_out(Vc, nb, Z, b, b, unused, unused2)) != SPMM_OK) return st;
-            if ((st = svqb(Z, b, Dst, ldv)) != SPMM_OK) return st;
-            hipError_t e = hipMemcpy2DAsync(Z, b * sizeof(float), Dst, ldv * sizeof(float), b * sizeof(float),
-                                            (size_t)n, hipMemcpyDeviceToDevice, s);
+            if ((st = svqb(Z, b, Dst, b)) != SPMM_OK) return st;
+            hipError_t e = hipMemcpyAsync(Z, Dst, (size_t)n * b * sizeof(float), hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return hip_fail(e, "basis block copy");
         }
         // second pass for orthogonality within the block
-        if ((st = svqb(Z, b, Dst, ldv, {}, {}, &s2)) != SPMM_OK) return st;
+        if ((st = svqb(Z, b, Dst, b, {}, {}, &s2)) != SPMM_OK) return st;
         R.resize((size_t)b * b);
         if (r == b) {
             // W = Z G1^{1/2} and Z = Dst G2^{1/2}, so R = G2^{1/2} G1^{1/2}:
@@ -340,7 +341,7 @@ struct Solver {
                 }
             return SPMM_OK;
         }
-        if ((st = tn(Dst, ldv, b, W, b, b, dC)) != SPMM_OK) return st;
+        if ((st = tn(Dst, spmm::row_major(b), b, W, b, b, dC)) != SPMM_OK) return st;
         if ((st = get(R.data(), dC, R.size())) != SPMM_OK) return st;
         return sync("block orthonormalisation");
     }
@@ -362,7 +363,7 @@ extern "C" spmm_status_t spmm_dense_tn(const float* A, int64_t lda, int p, const
     if (lda < p || ldb < q) return fail(SPMM_EINVAL, "lda must be >= p and ldb >= q");
     if (!C || !work || (n > 0 && (!A || !B))) return fail(SPMM_EINVAL, "NULL argument");
     if (work_bytes < spmm_dense_tn_workspace(n, p, q)) return fail(SPMM_EINVAL, "workspace too small");
-    hipError_t e = spmm::launch_ts_tn(A, lda, p, B, ldb, q, n, static_cast<double*>(work), C, s);
+    hipError_t e = spmm::launch_ts_tn(A, spmm::row_major(lda), p, B, ldb, q, n, static_cast<double*>(work), C, s);
     return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis product launch");
 }
 
@@ -371,7 +372,7 @@ extern "C" spmm_status_t spmm_dense_nn(const float* A, int64_t lda, int p, const
     if (p < 1 || q < 1 || n < 0) return fail(SPMM_EINVAL, "need p >= 1, q >= 1, n >= 0");
     if (lda < p || ldw < q) return fail(SPMM_EINVAL, "lda must be >= p and ldw >= q");
     if (n > 0 && (!A || !C || !W)) return fail(SPMM_EINVAL, "NULL argument");
-    hipError_t e = spmm::launch_ts_nn(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
+    hipError_t e = spmm::launch_ts_nn(A, spmm::row_major(lda), p, C, q, alpha, beta, W, spmm::row_major(ldw), n, s);
     return e == hipSuccess ? SPMM_OK : hip_fail(e, "basis update launch");
 }
 
@@ -446,11 +447,10 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
             s = own.compute;
         }
 
-        const int ldv = ((m + b + 3) / 4) * 4;
         spmm_abi::DevBufs bufs;
-        Solver S{h, H, s, own.copy, n, b, m, ldv};
-        S.V[0] = bufs.get<float>((size_t)n * ldv);
-        S.V[1] = bufs.get<float>((size_t)n * ldv);
+        Solver S{h, H, s, own.copy, n, b, m, spmm::ColLayout{b, b, n * b}};
+        S.V[0] = bufs.get<float>((size_t)n * (m + b));
+        S.V[1] = bufs.get<float>((size_t)n * (m + b));
         S.W = bufs.get<float>((size_t)n * b);
         S.Z = bufs.get<float>((size_t)n * b);
         S.part = bufs.get<double>(spmm::ts_partial_doubles());
@@ -488,8 +488,9 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
             // expand the basis to m columns, one block at a time
             while (cur < m) {
                 const int nb = cur + b;
-                if ((st = S.product(Vc + cur, S.W)) != SPMM_OK) return st;
-                if ((st = S.orthonormalise(Vc, nb, Vc + nb, coef, R)) != SPMM_OK) return st;
+                // basis column c starts block c / b, at Vc + c n (c a multiple of b)
+                if ((st = S.product(Vc + (size_t)cur * n, S.W)) != SPMM_OK) return st;
+                if ((st = S.orthonormalise(Vc, nb, Vc + (size_t)nb * n, coef, R)) != SPMM_OK) return st;
                 for (int r = 0; r < nb; ++r)
                     for (int x = 0; x < b; ++x) {
                         const double v = coef[(size_t)r * b + x];
@@ -543,7 +544,7 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
             for (int x = 0; x < b; ++x) C[(size_t)(m + x) * q + p + x] = 1.0;
             if ((st = S.put(S.dM, C.data(), C.size())) != SPMM_OK) return st;
             float* Vn = S.V[1 - cur_buf];
-            if ((st = S.nn(Vc, ldv, m + b, S.dM, q, 0.0, 1.0, Vn, ldv)) != SPMM_OK) return st;
+            if ((st = S.nn(Vc, S.VL, m + b, S.dM, q, 0.0, 1.0, Vn, S.VL)) != SPMM_OK) return st;
             cur_buf = 1 - cur_buf;
             Vc = Vn;
             std::fill(T.begin(), T.end(), 0.0);
@@ -569,7 +570,7 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
             for (int a = 0; a < m; ++a)
                 for (int c = 0; c < nev; ++c) C[(size_t)a * nev + c] = Sv[(size_t)a * m + order[c]];
             if ((st = S.put(S.dM, C.data(), C.size())) != SPMM_OK) return st;
-            if ((st = S.nn(Vc, ldv, m, S.dM, nev, 0.0, 1.0, evecs, ldvec)) != SPMM_OK) return st;
+            if ((st = S.nn(Vc, S.VL, m, S.dM, nev, 0.0, 1.0, evecs, spmm::row_major(ldvec))) != SPMM_OK) return st;
         }
         if ((st = S.sync("eigensolver")) != SPMM_OK) return st;
         double dense_ms = 0.0;

@@ -44,7 +44,7 @@ __device__ inline int pow2_at_least(int x) {
 // in flight before its first FMA; invalid rows and columns contribute 0.
 // The lanes' FP64 sums are then added in a fixed order through LDS.
 template <int Q>
-__global__ __launch_bounds__(kTsThreads) void ts_tn_partial_kernel(const float* __restrict__ A, int64_t lda, int p,
+__global__ __launch_bounds__(kTsThreads) void ts_tn_partial_kernel(const float* __restrict__ A, ColLayout LA, int p,
                                                                    const float* __restrict__ B, int64_t ldb, int q,
                                                                    int64_t n, double* __restrict__ part) {
     __shared__ double smem[kTsThreads * Q];   // B batches during the sweep, then the lanes' sums
@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kTsThreads) void ts_tn_partial_kernel(const float* 
     const int RB = rs * U;                                        // rows per batch (<= 64)
     const int slot = lane / ncol, col = lane - (lane / ncol) * ncol;
     const bool active = col < pc;
-    const float* ac = A + a0 + (active ? col : 0);
+    const float* ac = A + col_off(LA, a0 + (active ? col : 0));
+    const int64_t lda = LA.ld;
     const int64_t per = (n + nblk - 1) / nblk;
     const int64_t r0 = std::min<int64_t>(n, (int64_t)blockIdx.x * per);
     const int64_t r1 = std::min<int64_t>(n, r0 + per);
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kTsThreads) void ts_tn_final_kernel(const double* _
 // through LDS so that W is read and written with consecutive lanes on
 // consecutive elements.
 template <int QC, int CW>
-__global__ __launch_bounds__(kTsThreads) void ts_nn_kernel(const float* __restrict__ A, int64_t lda, int p,
+__global__ __launch_bounds__(kTsThreads) void ts_nn_kernel(const float* __restrict__ A, ColLayout LA, int p,
                                                            const double* __restrict__ C, int q, double alpha,
                                                            double beta, float* __restrict__ W, int64_t ldw,
                                                            int64_t n) {
@@ -158,10 +159,11 @@ __global__ __launch_bounds__(kTsThreads) void ts_nn_kernel(const float* __restri
         const int pw = min(CW, p - a0);
         // thread t loads column t % CW of rows t / CW + (256 / CW) j
         float v[CW];
+        const float* ap = A + col_off(LA, a0 + min(cc, pw - 1));
 #pragma unroll
         for (int j = 0; j < CW; ++j) {
             const int r = min(threadIdx.x / CW + j * kRowsPerPass, rows - 1);
-            v[j] = A[(row0 + r) * lda + a0 + min(cc, pw - 1)];
+            v[j] = ap[(row0 + r) * LA.ld];
         }
 #pragma unroll
         for (int j = 0; j < CW; ++j) sa[(threadIdx.x / CW + j * kRowsPerPass) * (CW + 1) + cc] = cc < pw ? v[j] : 0.0f;
@@ -192,9 +194,9 @@ __global__ __launch_bounds__(kTsThreads) void ts_nn_kernel(const float* __restri
 // W = alpha W + beta A C for wide C (the restart and the Ritz vectors): a
 // 64-row x 64-column tile of W per block, 4 x 4 of it per thread, with
 // 32-column slices of A and the matching 32 x 64 slice of C staged in LDS.
-__global__ __launch_bounds__(kTsThreads) void ts_nn_wide_kernel(const float* __restrict__ A, int64_t lda, int p,
+__global__ __launch_bounds__(kTsThreads) void ts_nn_wide_kernel(const float* __restrict__ A, ColLayout LA, int p,
                                                                 const double* __restrict__ C, int q, double alpha,
-                                                                double beta, float* __restrict__ W, int64_t ldw,
+                                                                double beta, float* __restrict__ W, ColLayout LW,
                                                                 int64_t n) {
     constexpr int TR = 64, TC = 64, KA = 32;
     __shared__ float sa[TR * (KA + 1)];
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(kTsThreads) void ts_nn_wide_kernel(const float* __r
         for (int j = 0; j < TR * KA / kTsThreads; ++j) {
             const int e = threadIdx.x + kTsThreads * j;
             const int r = min(e / KA, rows - 1), k = min(e % KA, pw - 1);
-            v[j] = A[(row0 + r) * lda + a0 + k];
+            v[j] = A[col_off(LA, a0 + k) + (row0 + r) * LA.ld];
         }
         double u[KA * TC / kTsThreads];
 #pragma unroll
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(kTsThreads) void ts_nn_wide_kernel(const float* __r
         for (int j = 0; j < 4; ++j) {
             const int c = 4 * tx + j;
             if (c >= cols) continue;
-            float* w = W + (row0 + r) * ldw + c0 + c;
+            float* w = W + col_off(LW, c0 + c) + (row0 + r) * LW.ld;
             const double old = alpha != 0.0 ? alpha * (double)*w : 0.0;
             *w = (float)(old + beta * acc[i][j]);
         }
@@ -292,9 +294,10 @@ int ts_max_outputs() { return kTsMaxOut; }
 int ts_max_width() { return kTsMaxP; }
 size_t ts_partial_doubles() { return (size_t)kTsMaxBlocks * kTsMaxOut; }
 
-hipError_t launch_ts_tn(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q, int64_t n,
+hipError_t launch_ts_tn(const float* A, ColLayout LA, int p, const float* B, int64_t ldb, int q, int64_t n,
                         double* part, double* C, hipStream_t s) {
-    if (p < 1 || q < 1 || p > kTsMaxP || q > kTsMaxQ || p * q > kTsMaxOut || n < 0) return hipErrorInvalidValue;
+    if (p < 1 || q < 1 || p > kTsMaxP || q > kTsMaxQ || p * q > kTsMaxOut || n < 0 || LA.bw < 1)
+        return hipErrorInvalidValue;
     const int nblk = tn_blocks(n);
     if (n == 0) {
         // no rows: C = 0 (one empty row range)
@@ -303,46 +306,48 @@ hipError_t launch_ts_tn(const float* A, int64_t lda, int p, const float* B, int6
     }
     const dim3 grid(nblk, (p + kTnCols - 1) / kTnCols);
     if (q == 1)
-        hipLaunchKernelGGL(ts_tn_partial_kernel<1>, grid, dim3(kTsThreads), 0, s, A, lda, p, B, ldb, q, n, part);
+        hipLaunchKernelGGL(ts_tn_partial_kernel<1>, grid, dim3(kTsThreads), 0, s, A, LA, p, B, ldb, q, n, part);
     else if (q == 2)
-        hipLaunchKernelGGL(ts_tn_partial_kernel<2>, grid, dim3(kTsThreads), 0, s, A, lda, p, B, ldb, q, n, part);
+        hipLaunchKernelGGL(ts_tn_partial_kernel<2>, grid, dim3(kTsThreads), 0, s, A, LA, p, B, ldb, q, n, part);
     else if (q <= 4)
-        hipLaunchKernelGGL(ts_tn_partial_kernel<4>, grid, dim3(kTsThreads), 0, s, A, lda, p, B, ldb, q, n, part);
+        hipLaunchKernelGGL(ts_tn_partial_kernel<4>, grid, dim3(kTsThreads), 0, s, A, LA, p, B, ldb, q, n, part);
     else if (q <= 8)
-        hipLaunchKernelGGL(ts_tn_partial_kernel<8>, grid, dim3(kTsThreads), 0, s, A, lda, p, B, ldb, q, n, part);
+        hipLaunchKernelGGL(ts_tn_partial_kernel<8>, grid, dim3(kTsThreads), 0, s, A, LA, p, B, ldb, q, n, part);
     else
-        hipLaunchKernelGGL(ts_tn_partial_kernel<16>, grid, dim3(kTsThreads), 0, s, A, lda, p, B, ldb, q, n, part);
+        hipLaunchKernelGGL(ts_tn_partial_kernel<16>, grid, dim3(kTsThreads), 0, s, A, LA, p, B, ldb, q, n, part);
     hipLaunchKernelGGL(ts_tn_final_kernel, dim3(p * q), dim3(kTsThreads), 0, s, part, nblk, C);
     return hipGetLastError();
 }
 
 template <int QC>
-static void launch_nn_q(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta,
+static void launch_nn_q(const float* A, ColLayout LA, int p, const double* C, int q, double alpha, double beta,
                         float* W, int64_t ldw, int64_t n, hipStream_t s) {
     const dim3 grid((unsigned)((n + kTsThreads - 1) / kTsThreads));
     if (p <= 8)
-        hipLaunchKernelGGL((ts_nn_kernel<QC, 8>), grid, dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+        hipLaunchKernelGGL((ts_nn_kernel<QC, 8>), grid, dim3(kTsThreads), 0, s, A, LA, p, C, q, alpha, beta, W, ldw, n);
     else
-        hipLaunchKernelGGL((ts_nn_kernel<QC, 32>), grid, dim3(kTsThreads), 0, s, A, lda, p, C, q, alpha, beta, W, ldw, n);
+        hipLaunchKernelGGL((ts_nn_kernel<QC, 32>), grid, dim3(kTsThreads), 0, s, A, LA, p, C, q, alpha, beta, W, ldw, n);
 }
 
-hipError_t launch_ts_nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta,
-                        float* W, int64_t ldw, int64_t n, hipStream_t s) {
-    if (p < 1 || q < 1 || n < 0) return hipErrorInvalidValue;
+hipError_t launch_ts_nn(const float* A, ColLayout LA, int p, const double* C, int q, double alpha, double beta,
+                        float* W, ColLayout LW, int64_t n, hipStream_t s) {
+    if (p < 1 || q < 1 || n < 0 || LA.bw < 1 || LW.bw < 1) return hipErrorInvalidValue;
     if (n == 0) return hipSuccess;
-    if (q == 1)
-        launch_nn_q<1>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
-    else if (q == 2)
-        launch_nn_q<2>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
-    else if (q <= 4)
-        launch_nn_q<4>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
-    else if (q <= 8)
-        launch_nn_q<8>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
-    else if (q <= 16)
-        launch_nn_q<16>(A, lda, p, C, q, alpha, beta, W, ldw, n, s);
+    // the row-per-thread kernel writes W as one row-major block
+    const bool one_block = q <= LW.bw;
+    if (one_block && q == 1)
+        launch_nn_q<1>(A, LA, p, C, q, alpha, beta, W, LW.ld, n, s);
+    else if (one_block && q == 2)
+        launch_nn_q<2>(A, LA, p, C, q, alpha, beta, W, LW.ld, n, s);
+    else if (one_block && q <= 4)
+        launch_nn_q<4>(A, LA, p, C, q, alpha, beta, W, LW.ld, n, s);
+    else if (one_block && q <= 8)
+        launch_nn_q<8>(A, LA, p, C, q, alpha, beta, W, LW.ld, n, s);
+    else if (one_block && q <= 16)
+        launch_nn_q<16>(A, LA, p, C, q, alpha, beta, W, LW.ld, n, s);
     else
         hipLaunchKernelGGL(ts_nn_wide_kernel, dim3((unsigned)((n + 63) / 64), (q + 63) / 64), dim3(kTsThreads), 0, s,
-                           A, lda, p, C, q, alpha, beta, W, ldw, n);
+                           A, LA, p, C, q, alpha, beta, W, LW, n);
     return hipGetLastError();
 }
 

@@ -245,16 +245,31 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int np, flo
 // probe_kernels.hip: one streaming read of bytes (a multiple of 16) at buf
 hipError_t launch_read_probe(const void* buf, uint64_t bytes, float* sink, hipStream_t s);
 
+// Layout of a tall FP32 block of columns: element (i, c) is at
+// base + (c / bw) * bstride + (c % bw) + i * ld.  Row-major with row stride
+// ld: bw at least the column count and bstride 0.  Column-blocked (arrays of
+// bw columns, each n x bw contiguous, bstride elements apart): ld = bw.
+struct ColLayout {
+    int64_t ld;
+    int32_t bw;
+    int64_t bstride;
+};
+inline ColLayout row_major(int64_t ld) { return ColLayout{ld, 0x7fffffff, 0}; }
+__host__ __device__ inline int64_t col_off(const ColLayout& L, int c) {
+    return (int64_t)(c / L.bw) * L.bstride + (c % L.bw);
+}
+
 // Tall-skinny dense kernels of the eigensolver (FP32 data, FP64 arithmetic).
 int ts_max_outputs();          // largest p * q launch_ts_tn accepts
 int ts_max_width();            // largest p + q launch_ts_tn accepts
 size_t ts_partial_doubles();   // size of the part buffer launch_ts_tn needs
-// C (p x q FP64, row-major) = A^T B; A n x p (stride lda), B n x q (stride ldb).
-hipError_t launch_ts_tn(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q, int64_t n,
+// C (p x q FP64, row-major) = A^T B; A n x p (layout LA), B n x q (stride ldb).
+hipError_t launch_ts_tn(const float* A, ColLayout LA, int p, const float* B, int64_t ldb, int q, int64_t n,
                         double* part, double* C, hipStream_t s);
-// W = alpha W + beta A C; A n x p, C p x q FP64, W n x q (must not alias A).
-hipError_t launch_ts_nn(const float* A, int64_t lda, int p, const double* C, int q, double alpha, double beta,
-                        float* W, int64_t ldw, int64_t n, hipStream_t s);
+// W = alpha W + beta A C; A n x p (layout LA), C p x q FP64, W n x q (layout
+// LW; must not alias A).
+hipError_t launch_ts_nn(const float* A, ColLayout LA, int p, const double* C, int q, double alpha, double beta,
+                        float* W, ColLayout LW, int64_t n, hipStream_t s);
 // X[i][c] (c < q <= 64) uniform in [-1/2, 1/2), a function of (seed, i, c).
 hipError_t launch_fill_uniform(float* X, int64_t ldx, int q, int64_t n, uint64_t seed, hipStream_t s);
 
