@@ -594,7 +594,7 @@ spmm_status_t spmm_dense_nn(const float* A, int64_t lda, int p, const double* C,
  *   a : host double n x n row-major, exactly symmetric (else SPMM_EINVAL).
  *   w : host double[n], ascending.   z : host double n x n row-major,
  *       column j the unit eigenvector of w[j].
- * 1 <= n <= 4096.  No device work.
+ * 1 <= n <= 1024 (each Jacobi sweep costs O(n^3)).  No device work.
  */
 spmm_status_t spmm_sym_eig_small(int n, const double* a, double* w, double* z);
 

@@ -377,7 +377,7 @@ extern "C" spmm_status_t spmm_dense_nn(const float* A, int64_t lda, int p, const
 }
 
 extern "C" spmm_status_t spmm_sym_eig_small(int n, const double* a, double* w, double* z) {
-    if (n < 1 || n > 4096 || !a || !w || !z) return fail(SPMM_EINVAL, "need 1 <= n <= 4096 and non-NULL arrays");
+    if (n < 1 || n > 1024 || !a || !w || !z) return fail(SPMM_EINVAL, "need 1 <= n <= 1024 and non-NULL arrays");
     std::vector<double> A(a, a + (size_t)n * n), wv, zv;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < i; ++j)

@@ -48,6 +48,7 @@ def test_jacobi_closed_forms():
 def test_jacobi_rejects_bad_input():
     assert _err(pk.spmm_sym_eig_small, np.array([[1.0, 2.0], [2.5, 1.0]])).status == pk.SPMM_EINVAL
     assert _err(pk.spmm_sym_eig_small, np.zeros((0, 0))).status == pk.SPMM_EINVAL
+    assert _err(pk.spmm_sym_eig_small, np.eye(1025)).status == pk.SPMM_EINVAL
 
 
 def test_eigs_argument_checks_before_device():
