@@ -1,7 +1,9 @@
 // Dense kernels of the block Krylov-Schur eigensolver.  The basis V is a
-// tall, narrow FP32 matrix (n rows, at most a few hundred columns, row-major):
-//   ts_tn   C = A^T B            (A n x p, p <= 512, B n x q, q <= 16, p q <= 2048;
-//                                 C p x q FP64, row-major)
+// tall, narrow FP32 matrix (n rows, at most a few hundred columns), row-major
+// or stored as contiguous blocks of columns (a ColLayout gives the address
+// of element (i, c)):
+//   ts_tn   C = A^T B            (A n x p, p <= 512, B n x q row-major, q <= 16,
+//                                 p q <= 2048; C p x q FP64, row-major)
 //   ts_nn   W = alpha W + beta A C   (C p x q FP64; W must not alias A)
 //   fill_uniform  X[i][c] uniform in [-1/2, 1/2) from a counter-based hash.
 // Products are exact in FP64 (two FP32 factors) and sums are FP64 in a fixed
@@ -131,8 +133,8 @@ __global__ __launch_bounds__(kTsThreads) void ts_tn_final_kernel(const double* _
     if (threadIdx.x == 0) C[o] = red[0];
 }
 
-// W = alpha W + beta A C for q <= 16 output columns (QC >= q): one thread
-// per row, 256 rows per block.  A is staged through LDS CW columns at a
+// W = alpha W + beta A C for q <= 16 output columns (QC >= q), W row-major
+// with row stride ldw: one thread per row, 256 rows per block.  A is staged through LDS CW columns at a
 // time with coalesced loads (row stride CW + 1 floats: the per-thread row
 // reads hit distinct banks), with the matching CW rows of C (every thread
 // reads the same entry: a broadcast).  The block's 256 x q results go back
