@@ -45,7 +45,8 @@ typedef enum {
     SPMM_ENOTCONV = -6       /* an iterative method stopped before converging */
 } spmm_status_t;
 
-/* Element type of X.  Accumulation is always FP32 and Y is always FP32. */
+/* Element type of X.  Y is always FP32; how the products are summed is
+ * described at spmm_run. */
 typedef enum {
     SPMM_X_F32 = 0,
     SPMM_X_BF16 = 1,       /* round-to-nearest-even of the FP32 value          */
@@ -124,7 +125,7 @@ typedef struct spmm_handle_s* spmm_handle_t;
 
 /*
  * Convert a CSR matrix into the tile store (the CSR -> SCSR conversion of
- * Section 6, Table 3).  Host work only: the device copy is made by the
+ * Section 5, Table 3).  Host work only: the device copy is made by the
  * first spmm_run (or the pinned host copy by the first spmm_stream_run).
  *   n_rows, n_cols : matrix shape, 0 <= n <= 2^31 - 1.
  *   row_ptr        : host int64[n_rows + 1], row_ptr[0] = 0, non-decreasing.

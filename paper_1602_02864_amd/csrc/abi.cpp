@@ -8,6 +8,7 @@
 #include <string>
 
 #include "abi_internal.h"
+#include "stream_plan.h"
 
 namespace spmm_abi {
 
@@ -77,25 +78,7 @@ spmm_status_t upload(spmm::Handle& H) {
         if ((e = hipHostMalloc(&H.h_blob, nb, hipHostMallocDefault)) != hipSuccess)
             return fail(SPMM_ENOMEM, "hipHostMalloc(tile payload) failed");
         if (E.blob.size()) std::memcpy(H.h_blob, E.blob.data(), E.blob.size());
-        // consecutive items whose payload adds up to about stream_bytes form
-        // one transfer group (items are laid out back to back in the blob)
-        H.groups.clear();
-        const uint64_t ni = E.items.size();
-        uint64_t i0 = 0;
-        while (i0 < ni) {
-            const uint64_t b0 = E.items[i0].blob_off;
-            uint64_t i1 = i0 + 1;
-            while (i1 < ni && E.items[i1].blob_off - b0 < H.stream_bytes) ++i1;
-            // never split the pieces of one split row across groups: each
-            // launch must see all pieces of a row, so that its per-row
-            // counter and partial slots are used by one column chunk at a time
-            while (i1 < ni && E.items[i1].part >= 0 && E.items[i1 - 1].part >= 0 &&
-                   E.items[i1].cid == E.items[i1 - 1].cid)
-                ++i1;
-            const uint64_t b1 = i1 < ni ? E.items[i1].blob_off : (uint64_t)E.blob.size();
-            H.groups.push_back({i0, i1, b0, b1});
-            i0 = i1;
-        }
+        H.groups = spmm::make_groups(E, H.stream_bytes);
     }
     const size_t ni = E.items.size() ? E.items.size() : 1;
     if ((e = hipMalloc(&H.d_items, ni * sizeof(spmm::ItemDesc))) != hipSuccess)
@@ -404,14 +387,6 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
                 H.ring_used.push_back(0);
             }
         }
-        // Calls do not overlap: before this call copies into the ring, the
-        // host waits until the kernels of the previous call have finished
-        // reading it (the copies within one call are ordered by events).
-        for (size_t r = 0; r < H.ring.size(); ++r) {
-            if (!H.ring_used[r]) continue;
-            hipError_t e = hipEventSynchronize(H.ev_free[r]);
-            if (e != hipSuccess) return hip_fail(e, "previous streamed call");
-        }
         spmm::RunArgs a{};
         if ((st = prepare_x(H, X, k, ldx, dt, compute, false, a)) != SPMM_OK) return st;
         a.dtype = dt;
@@ -422,30 +397,39 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
         a.combine = H.d_combine;
         a.n_combine = (uint32_t)H.enc.combine.size();
         a.count = H.d_count;
-        const uint32_t R = (uint32_t)H.ring.size();
-        for (size_t g = 0; g < H.groups.size(); ++g) {
-            const auto& G = H.groups[g];
-            const uint32_t slot = (uint32_t)(g % R);
-            hipError_t e;
-            // the copy into a slot waits until the kernels reading its
-            // previous group are done; the kernels wait for their copy
-            // also across calls: the previous call's last kernels may still
-            // be reading the slot this call's first copies fill
-            if (H.ring_used[slot] && (e = hipStreamWaitEvent(copy, H.ev_free[slot], 0)) != hipSuccess)
-                return hip_fail(e, "wait");
-            if ((e = hipMemcpyAsync(H.ring[slot], static_cast<uint8_t*>(H.h_blob) + G.b0, G.b1 - G.b0,
-                                    hipMemcpyHostToDevice, copy)) != hipSuccess)
-                return hip_fail(e, "hipMemcpyAsync(tile group)");
-            if ((e = hipEventRecord(H.ev_ready[slot], copy)) != hipSuccess) return hip_fail(e, "record");
-            if ((e = hipStreamWaitEvent(compute, H.ev_ready[slot], 0)) != hipSuccess) return hip_fail(e, "wait");
-            a.blob = static_cast<const uint8_t*>(H.ring[slot]);
-            a.blob_bias = G.b0;
-            a.items = H.d_items + G.i0;
-            a.n_items = (uint32_t)(G.i1 - G.i0);
-            if ((e = spmm::launch_spmm(H, a)) != hipSuccess) return hip_fail(e, "kernel launch");
-            if ((e = hipEventRecord(H.ev_free[slot], compute)) != hipSuccess) return hip_fail(e, "record");
-            H.ring_used[slot] = 1;
-        }
+        // The slot/event ordering of the ring (stream_plan.h): every copy
+        // into a slot waits for the kernels that last read it, also across
+        // calls, so consecutive calls need no host synchronisation.
+        struct HipOps {
+            spmm::Handle& H;
+            spmm::RunArgs& a;
+            hipStream_t kstream, cstream;  // compute, copy
+            spmm_status_t st = SPMM_OK;
+            bool check(hipError_t e, const char* what) {
+                if (e == hipSuccess) return true;
+                st = hip_fail(e, what);
+                return false;
+            }
+            bool wait_free(uint32_t s) { return check(hipStreamWaitEvent(cstream, H.ev_free[s], 0), "wait (slot free)"); }
+            bool copy(uint64_t g, uint32_t s) {
+                const auto& G = H.groups[g];
+                return check(hipMemcpyAsync(H.ring[s], static_cast<uint8_t*>(H.h_blob) + G.b0, G.b1 - G.b0,
+                                            hipMemcpyHostToDevice, cstream),
+                             "hipMemcpyAsync(tile group)");
+            }
+            bool record_ready(uint32_t s) { return check(hipEventRecord(H.ev_ready[s], cstream), "record (slot ready)"); }
+            bool wait_ready(uint32_t s) { return check(hipStreamWaitEvent(kstream, H.ev_ready[s], 0), "wait (slot ready)"); }
+            bool launch(uint64_t g, uint32_t s) {
+                const auto& G = H.groups[g];
+                a.blob = static_cast<const uint8_t*>(H.ring[s]);
+                a.blob_bias = G.b0;
+                a.items = H.d_items + G.i0;
+                a.n_items = (uint32_t)(G.i1 - G.i0);
+                return check(spmm::launch_spmm(H, a), "kernel launch");
+            }
+            bool record_free(uint32_t s) { return check(hipEventRecord(H.ev_free[s], kstream), "record (slot free)"); }
+        } ops{H, a, compute, copy};
+        if (!spmm::run_stream_plan(H.groups.size(), (uint32_t)H.ring.size(), H.ring_used.data(), ops)) return ops.st;
         return SPMM_OK;
     } catch (const std::exception& ex) {
         return fail(SPMM_EINVAL, ex.what());

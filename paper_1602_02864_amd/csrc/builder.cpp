@@ -4,7 +4,7 @@
 // matrix is cut into h x w tiles, tiles of one tile row ("slab") are kept in
 // column order, and every entry is a 16-bit local row and a 16-bit local
 // column inside its tile.  Conversion is one linear pass over the CSR
-// (Section 6, Table 3).  The encoder then turns each slab into work items
+// (Section 5, Table 3).  The encoder then turns each slab into work items
 // for the GPU, routing every row of every tile to the lane mapping its tile
 // variant asks for (COO pairs, one lane per row, or one wavefront per row).
 #include <algorithm>
@@ -550,6 +550,28 @@ void encode_slab(const Handle& H, uint64_t s, ChunkOut& out, Scratch& S) {
 }
 
 }  // namespace
+
+std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes) {
+    // consecutive items whose payload adds up to about stream_bytes form one
+    // transfer group (items are laid out back to back in the blob)
+    std::vector<Handle::Group> groups;
+    const uint64_t ni = E.items.size();
+    uint64_t i0 = 0;
+    while (i0 < ni) {
+        const uint64_t b0 = E.items[i0].blob_off;
+        uint64_t i1 = i0 + 1;
+        while (i1 < ni && E.items[i1].blob_off - b0 < stream_bytes) ++i1;
+        // never split the pieces of one split row across groups: each launch
+        // must see all pieces of a row, so that its per-row counter and
+        // partial slots are used by one column chunk at a time
+        while (i1 < ni && E.items[i1].part >= 0 && E.items[i1 - 1].part >= 0 && E.items[i1].cid == E.items[i1 - 1].cid)
+            ++i1;
+        const uint64_t b1 = i1 < ni ? E.items[i1].blob_off : (uint64_t)E.blob.size();
+        groups.push_back({i0, i1, b0, b1});
+        i0 = i1;
+    }
+    return groups;
+}
 
 spmm_status_t encode(Handle& H, std::string& err) {
     const uint64_t S = H.n_slabs;

@@ -180,6 +180,9 @@ spmm_status_t encode(Handle& H, std::string& err);
 spmm_status_t transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr, const int32_t* col,
                             const float* val, uint32_t threads, std::vector<int64_t>& tp, std::vector<int32_t>& tc,
                             std::vector<float>& tv, std::string& err);
+// Transfer groups of streamed mode: consecutive items of about stream_bytes
+// of payload, never splitting the pieces of one split row.
+std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes);
 spmm_status_t decode(const Handle& H, int64_t* row_ptr, int32_t* col, float* val, std::string& err);
 void tile_features(const Handle& H, int k, int xbytes, float* out);
 spmm_status_t model_tiles(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr,

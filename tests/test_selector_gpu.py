@@ -217,7 +217,6 @@ def test_trained_selector_gain_on_held_out_graph():
     print("mean regret over the per-bucket optimum:", {a: round(m, 4) for a, m in mean.items()})
     assert mean["learned"] <= 0.05
     assert max(regret["learned"]) <= 0.10
-    # faster than the paper's own fixed layout (SCSR rows + COO single-entry
-    # rows, the ROW variant), and never far from the best single format
-    assert mean["learned"] < mean["row"]
-    assert mean["learned"] <= min(mean[name] for name in pk.VARIANT_NAMES) + 0.01
+    # faster than every single fixed format, the paper's own layout (SCSR
+    # rows + COO single-entry rows, the ROW variant) included
+    assert mean["learned"] < min(mean[name] for name in pk.VARIANT_NAMES)
