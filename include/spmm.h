@@ -105,7 +105,7 @@ typedef struct {
                                  in-degree, and spmm_run first gathers X into that
                                  row order (a handle-owned buffer), so the X rows
                                  of hub columns are contiguous and cache-resident;
-                                 1: tiles keep the given column order             */
+                                 1: tiles keep the given column and row order     */
     uint32_t stream_kib;     /* streamed mode: payload per host->device transfer
                                  group, KiB; 0 -> 262144 (256 MiB)                 */
     uint32_t ring_depth;     /* streamed mode: device slots in the transfer ring;
@@ -119,6 +119,14 @@ typedef struct {
                                  transposed on the host first (for PageRank's
                                  in-link matrix and NMF's A^T on a directed
                                  graph); its shape is then n_cols x n_rows       */
+    uint32_t keep_row_order; /* 0 (default, unless keep_order = 1): tile rows take
+                                 the rows in order of descending out-degree (ties
+                                 by row id), so that rows sharing hub columns
+                                 share tile rows and gather those X rows once;
+                                 Y is still written in the given row order, and
+                                 rows without entries are zero-filled.  1 (or
+                                 keep_order = 1): tile rows take the given row
+                                 order                                           */
 } spmm_build_opts;
 
 typedef struct spmm_handle_s* spmm_handle_t;

@@ -62,7 +62,7 @@ class spmm_build_opts(ctypes.Structure):
                 ("validate", ctypes.c_uint32), ("max_kc", ctypes.c_uint32),
                 ("keep_order", ctypes.c_uint32), ("stream_kib", ctypes.c_uint32),
                 ("ring_depth", ctypes.c_uint32), ("x_stage_kib", ctypes.c_int32),
-                ("transpose", ctypes.c_uint32)]
+                ("transpose", ctypes.c_uint32), ("keep_row_order", ctypes.c_uint32)]
 
 
 class spmm_stats_t(ctypes.Structure):
@@ -240,7 +240,7 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
                      item_nnz: int = 0, place: int = SPMM_PLACE_DEVICE, threads: int = 0,
                      validate: bool = True, max_kc: int = 0, keep_order: bool = False,
                      stream_kib: int = 0, ring_depth: int = 0, x_stage_kib: int = 0,
-                     transpose: bool = False) -> Handle:
+                     transpose: bool = False, keep_row_order: bool = False) -> Handle:
     L = load_library()
     rp = _host(row_ptr, np.int64)
     ci = _host(col_idx, np.int32)
@@ -249,7 +249,7 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
     n_cols = n_rows if n_cols is None else int(n_cols)
     o = spmm_build_opts(tile_rows, tile_cols, fixed_variant, item_nnz, place, threads,
                         int(bool(validate)), max_kc, int(bool(keep_order)), stream_kib, ring_depth,
-                        int(x_stage_kib), int(bool(transpose)))
+                        int(x_stage_kib), int(bool(transpose)), int(bool(keep_row_order)))
     out = ctypes.c_void_p()
     st = L.spmm_build_tiles(n_rows, n_cols, rp.ctypes.data, None if ci is None or ci.size == 0 else ci.ctypes.data,
                             None if va is None else va.ctypes.data, ctypes.byref(o), ctypes.byref(out))

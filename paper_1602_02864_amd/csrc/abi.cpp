@@ -36,6 +36,8 @@ void free_device(spmm::Handle& H) {
     H.d_colmax = nullptr;
     H.d_fexp = nullptr;
     if (H.d_col_old) (void)hipFree(H.d_col_old);
+    if (H.d_row_old) (void)hipFree(H.d_row_old);
+    H.d_row_old = nullptr;
     if (H.d_col_count) (void)hipFree(H.d_col_count);
     H.d_col_count = nullptr;
     if (H.d_xperm) (void)hipFree(H.d_xperm);
@@ -105,6 +107,13 @@ spmm_status_t upload(spmm::Handle& H) {
         if ((e = hipMemcpy(H.d_col_old, H.col_old.data(), sizeof(int32_t) * (size_t)H.n_cols,
                            hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "hipMemcpy(column order)");
+    }
+    if (!H.row_old.empty()) {
+        if ((e = hipMalloc(&H.d_row_old, sizeof(int32_t) * H.row_old.size())) != hipSuccess)
+            return fail(SPMM_ENOMEM, "hipMalloc(row order) failed");
+        if ((e = hipMemcpy(H.d_row_old, H.row_old.data(), sizeof(int32_t) * H.row_old.size(),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy(row order)");
     }
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     if (H.place == SPMM_PLACE_PINNED_HOST) std::vector<uint8_t>().swap(E.blob);  // pinned copy replaces it
@@ -196,6 +205,13 @@ spmm_status_t prepare_x(spmm::Handle& H, const void* X, int k, int64_t ldx, int 
     return SPMM_OK;
 }
 
+// Rows without entries of a row-relabelled handle are not tiled: zero them.
+spmm_status_t zero_empty_rows(const spmm::Handle& H, float* Y, int64_t ldy, int k, hipStream_t s) {
+    if (!H.d_row_old || H.n_tiled_rows >= H.n_rows) return SPMM_OK;
+    hipError_t e = spmm::launch_zero_rows(Y, ldy, k, H.d_row_old + H.n_tiled_rows, H.n_rows - H.n_tiled_rows, s);
+    return e == hipSuccess ? SPMM_OK : hip_fail(e, "zero-row launch");
+}
+
 spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt, const float* col_scale,
                          float* Y, int64_t ldy, hipStream_t s, bool x_in_handle_order) {
     spmm::RunArgs a{};
@@ -213,6 +229,7 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
     a.combine = H.d_combine;
     a.n_combine = (uint32_t)H.enc.combine.size();
     a.count = H.d_count;
+    a.rmap = H.d_row_old;
     hipEvent_t* ev = nullptr;
     if (H.timing) {
         if (H.timing_used + 2 > H.timing_ev.size()) {
@@ -230,7 +247,7 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
     hipError_t e = spmm::launch_spmm(H, a);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    return SPMM_OK;
+    return zero_empty_rows(H, Y, ldy, k, s);
 }
 
 // The SpMM launches alone, with fixed-point exponents already in fexp and X
@@ -255,6 +272,7 @@ spmm_status_t launch_items_only(spmm::Handle& H, const void* X, int k, int64_t l
     a.combine = H.d_combine;
     a.n_combine = (uint32_t)H.enc.combine.size();
     a.count = H.d_count;
+    a.rmap = H.d_row_old;
     hipError_t e = spmm::launch_spmm(H, a);
     return e == hipSuccess ? SPMM_OK : hip_fail(e, "kernel launch");
 }
@@ -316,6 +334,7 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         H.place = o.place;
         H.max_kc = (int)o.max_kc;
         H.relabel = o.keep_order == 0;
+        H.row_relabel = o.keep_order == 0 && o.keep_row_order == 0;
         H.stream_bytes = (uint64_t)(o.stream_kib ? o.stream_kib : 262144u) << 10;
         H.ring_depth = o.ring_depth ? o.ring_depth : 3u;
         H.stage_bytes = o.x_stage_kib > 0 ? (uint64_t)o.x_stage_kib << 10 : 0u;
@@ -397,6 +416,7 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
         a.combine = H.d_combine;
         a.n_combine = (uint32_t)H.enc.combine.size();
         a.count = H.d_count;
+        a.rmap = H.d_row_old;
         // The slot/event ordering of the ring (stream_plan.h): every copy
         // into a slot waits for the kernels that last read it, also across
         // calls, so consecutive calls need no host synchronisation.
@@ -430,7 +450,7 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
             bool record_free(uint32_t s) { return check(hipEventRecord(H.ev_free[s], kstream), "record (slot free)"); }
         } ops{H, a, compute, copy};
         if (!spmm::run_stream_plan(H.groups.size(), (uint32_t)H.ring.size(), H.ring_used.data(), ops)) return ops.st;
-        return SPMM_OK;
+        return zero_empty_rows(H, Y, ldy, k, compute);
     } catch (const std::exception& ex) {
         return fail(SPMM_EINVAL, ex.what());
     }

@@ -121,7 +121,6 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
     H.nnz = nnz;
     H.has_val = val != nullptr;
     H.wshift = log2_exact(H.w);
-    H.n_slabs = (uint64_t)((n + H.h - 1) / H.h);
     H.n_strips = (uint64_t)((H.n_cols + H.w - 1) / H.w);
     if (H.n_strips == 0) H.n_strips = 1;
 
@@ -198,6 +197,48 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
     }
     auto colmap = [cmap](int32_t c) -> uint32_t { return cmap ? (uint32_t)cmap[c] : (uint32_t)c; };
 
+    // Row order.  With row relabelling, tile rows take the rows in order of
+    // descending out-degree (ties by row id), so that rows sharing the hub
+    // columns sit in the same tile rows and their X rows are gathered once
+    // per tile row; rows without entries come last and are not tiled (their
+    // Y rows are zero-filled).  rp_new is the prefix of row lengths in the
+    // tile order: the entries of tile row s start at rp_new[s * h] in ent.
+    H.row_old.clear();
+    H.n_tiled_rows = n;
+    std::vector<int64_t> rp_new;
+    if (H.row_relabel && n > 0) {
+        uint64_t maxd = 0;
+        for (int64_t r = 0; r < n; ++r) maxd = std::max<uint64_t>(maxd, (uint64_t)(row_ptr[r + 1] - row_ptr[r]));
+        // counting sort on key = cap - min(degree, cap) (descending degree,
+        // stable in row id); rows of degree >= cap share key 0 and are then
+        // ordered exactly
+        const uint64_t cap = std::min<uint64_t>(maxd, 1u << 20);
+        auto key = [&](int64_t r) -> uint64_t {
+            return cap - std::min<uint64_t>(cap, (uint64_t)(row_ptr[r + 1] - row_ptr[r]));
+        };
+        std::vector<uint64_t> start(cap + 2, 0);
+        for (int64_t r = 0; r < n; ++r) start[key(r) + 1]++;
+        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+        const uint64_t nbig = start[1];
+        H.row_old.resize((size_t)n);
+        for (int64_t r = 0; r < n; ++r) H.row_old[start[key(r)]++] = (int32_t)r;
+        std::stable_sort(H.row_old.begin(), H.row_old.begin() + (int64_t)nbig, [&](int32_t x, int32_t y) {
+            return row_ptr[x + 1] - row_ptr[x] > row_ptr[y + 1] - row_ptr[y];
+        });
+        int64_t live = n;
+        while (live > 0 && row_ptr[H.row_old[live - 1] + 1] == row_ptr[H.row_old[live - 1]]) --live;
+        H.n_tiled_rows = live;
+        rp_new.resize((size_t)live + 1);
+        rp_new[0] = 0;
+        for (int64_t r = 0; r < live; ++r) rp_new[r + 1] = rp_new[r] + (row_ptr[H.row_old[r] + 1] - row_ptr[H.row_old[r]]);
+    }
+    const int32_t* rmap = H.row_old.empty() ? nullptr : H.row_old.data();
+    auto row_begin = [&](int64_t r) -> int64_t { return rmap ? row_ptr[rmap[r]] : row_ptr[r]; };
+    auto row_end = [&](int64_t r) -> int64_t { return rmap ? row_ptr[rmap[r] + 1] : row_ptr[r + 1]; };
+    auto tiled_base = [&](int64_t r) -> int64_t { return rmap ? rp_new[r] : row_ptr[r]; };
+    const int64_t nt = H.n_tiled_rows;
+    H.n_slabs = (uint64_t)((nt + H.h - 1) / H.h);
+
     // Pass 1: non-empty tiles per slab.
     std::vector<uint64_t> ntile(H.n_slabs + 1, 0);
     const uint32_t nstrip = (uint32_t)H.n_strips;
@@ -205,12 +246,13 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
         std::vector<uint32_t> cnt(nstrip, 0);
         std::vector<uint32_t> used;
         for (uint64_t s = a; s < b; ++s) {
-            int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(n, r0 + H.h);
+            int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(nt, r0 + H.h);
             used.clear();
-            for (int64_t p = row_ptr[r0]; p < row_ptr[r1]; ++p) {
-                uint32_t J = colmap(col[p]) >> H.wshift;
-                if (cnt[J]++ == 0) used.push_back(J);
-            }
+            for (int64_t r = r0; r < r1; ++r)
+                for (int64_t p = row_begin(r); p < row_end(r); ++p) {
+                    uint32_t J = colmap(col[p]) >> H.wshift;
+                    if (cnt[J]++ == 0) used.push_back(J);
+                }
             ntile[s + 1] = used.size();
             for (uint32_t J : used) cnt[J] = 0;
         }
@@ -237,14 +279,15 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
         std::vector<uint64_t> seen((H.w + 63) / 64, 0);
         uint64_t my_nnr = 0, my_nnc = 0;
         for (uint64_t s = a; s < b; ++s) {
-            int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(n, r0 + H.h);
+            int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(nt, r0 + H.h);
             used.clear();
-            for (int64_t p = row_ptr[r0]; p < row_ptr[r1]; ++p) {
-                uint32_t J = colmap(col[p]) >> H.wshift;
-                if (cnt[J]++ == 0) used.push_back(J);
-            }
+            for (int64_t r = r0; r < r1; ++r)
+                for (int64_t p = row_begin(r); p < row_end(r); ++p) {
+                    uint32_t J = colmap(col[p]) >> H.wshift;
+                    if (cnt[J]++ == 0) used.push_back(J);
+                }
             std::sort(used.begin(), used.end());
-            uint64_t e = (uint64_t)row_ptr[r0];
+            uint64_t e = (uint64_t)tiled_base(r0);
             uint64_t t = H.slab_tiles[s];
             for (uint32_t J : used) {
                 Tile& tl = H.tiles[t++];
@@ -258,7 +301,7 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
             }
             for (int64_t r = r0; r < r1; ++r) {
                 uint32_t rl = (uint32_t)(r - r0);
-                for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
+                for (int64_t p = row_begin(r); p < row_end(r); ++p) {
                     uint32_t c = colmap(col[p]);
                     uint64_t q = pos[c >> H.wshift]++;
                     H.ent[q] = (rl << 16) | (c & (H.w - 1));
@@ -467,7 +510,7 @@ void emit_item(const Handle& H, uint32_t slab, uint32_t lo, uint32_t hi, int32_t
 void encode_slab(const Handle& H, uint64_t s, ChunkOut& out, Scratch& S) {
     const uint32_t C = H.item_nnz;
     const int64_t r0 = (int64_t)s * H.h;
-    const uint32_t nr = (uint32_t)std::min<int64_t>(H.h, H.n_rows - r0);
+    const uint32_t nr = (uint32_t)std::min<int64_t>(H.h, H.n_tiled_rows - r0);
     const uint64_t t0 = H.slab_tiles[s], t1 = H.slab_tiles[s + 1];
     S.rdeg.assign(nr, 0);
     S.cursor.resize(t1 - t0);
@@ -767,19 +810,28 @@ spmm_status_t decode(const Handle& H, int64_t* row_ptr, int32_t* col, float* val
         err = "decoded entry count differs from nnz";
         return SPMM_ESTATE;
     }
-    // every row must be written by exactly one owner: an item's row range,
-    // or the combine of a split row
-    std::vector<uint8_t> own((size_t)H.n_rows, 0);
+    // every tiled row must be written by exactly one owner: an item's row
+    // range, or the combine of a split row (rows past n_tiled_rows of a
+    // row-relabelled handle have no entries and are zero-filled)
+    std::vector<uint8_t> own((size_t)H.n_tiled_rows, 0);
     for (const ItemDesc& d : H.enc.items) {
         if (d.part >= 0) continue;
         const int64_t row0 = (int64_t)d.slab * H.h;
         for (uint32_t r = d.rows & 0xFFFFu; r < (d.rows >> 16); ++r) own[row0 + r]++;
     }
     for (const CombineDesc& c : H.enc.combine) own[(int64_t)c.slab * H.h + c.row]++;
-    for (int64_t r = 0; r < H.n_rows; ++r)
+    for (int64_t r = 0; r < H.n_tiled_rows; ++r)
         if (own[r] != 1) {
             err = "row " + std::to_string(r) + " has " + std::to_string(own[r]) + " owners";
             return SPMM_ESTATE;
+        }
+    if (!H.row_old.empty())
+        for (Trip& t : out) {
+            if (t.r < 0 || t.r >= H.n_tiled_rows) {
+                err = "decoded row out of range";
+                return SPMM_ESTATE;
+            }
+            t.r = H.row_old[(size_t)t.r];
         }
     if (H.relabel)
         for (Trip& t : out) t.c = H.col_old[(size_t)t.c];

@@ -143,6 +143,7 @@ void make_subset(const spmm::Handle& H, const std::vector<uint64_t>& sel, spmm::
     S.slab_tiles.push_back(sel.size());
     S.n_slabs = S.slab_tiles.size() - 1;
     S.n_rows = (int64_t)S.n_slabs * H.h;
+    S.n_tiled_rows = S.n_rows;
     S.nnz = (int64_t)nnz;
 }
 

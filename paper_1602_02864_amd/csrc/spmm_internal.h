@@ -129,6 +129,14 @@ struct Handle {
     uint32_t* d_col_count = nullptr;   // device copy (PageRank out-degrees)
     void* d_xperm = nullptr;           // X in relabelled row order
     uint64_t xperm_bytes = 0;
+    // Row relabelling: tile rows hold the rows in order of descending
+    // out-degree; rows [n_tiled_rows, n_rows) of that order have no entries
+    // and are zero-filled.  Without relabelling row_old is empty and
+    // n_tiled_rows = n_rows.
+    bool row_relabel = false;
+    std::vector<int32_t> row_old;      // original row of tiled row r
+    int64_t n_tiled_rows = 0;
+    int32_t* d_row_old = nullptr;      // device copy of row_old
     // encoded work
     Encoded enc;
     // device / pinned copies
@@ -209,8 +217,12 @@ struct RunArgs {
     uint32_t n_combine;
     uint32_t* count;             // device, n_combine counters, zero between launches
     const int32_t* fexp;         // device, per column of X: fixed-point exponent
+    const int32_t* rmap;         // device, original row of each tiled row (NULL: identity)
 };
 hipError_t launch_spmm(const Handle& H, const RunArgs& a);
+// Zero the k columns of the Y rows that have no entries (the original rows
+// rmap[n_tiled .. n_rows) of a row-relabelled handle).
+hipError_t launch_zero_rows(float* Y, int64_t ldy, int k, const int32_t* rows, int64_t count, hipStream_t s);
 // X prepared for a launch: optionally gathered into the handle's column
 // order (Xp row i = X row old_of_new[i], row stride ldp; Xp NULL = read in
 // place), and the per-column fixed-point exponents of the accumulators:

@@ -164,8 +164,8 @@ __device__ __forceinline__ void process_item(
     const ItemDesc& d, const uint8_t* __restrict__ blob, uint64_t blob_bias, const XT* __restrict__ X,
     int64_t ldx, float* __restrict__ Y, int64_t ldy, int64_t* __restrict__ part,
     const CombineDesc* __restrict__ combine, uint32_t* __restrict__ count, const float* __restrict__ yscale,
-    const int32_t* __restrict__ fexp, uint32_t h, uint32_t wshift, unsigned long long* acc, uint32_t* jt,
-    const float* xs, uint32_t ns, int lane) {
+    const int32_t* __restrict__ fexp, const int32_t* __restrict__ rmap, uint32_t h, uint32_t wshift,
+    unsigned long long* acc, uint32_t* jt, const float* xs, uint32_t ns, int lane) {
     constexpr bool has_val = HV;        // weighted A
     constexpr int G = KC / VW;          // lanes per X row
     constexpr int P = 64 / G;           // entries per step
@@ -360,10 +360,11 @@ __device__ __forceinline__ void process_item(
     const int64_t row0 = (int64_t)d.slab * h;
     if (d.part < 0) {
         const uint32_t total = (hi - lo) * KC;
-        float* yb = Y + (row0 + lo) * ldy;
         for (uint32_t i = lane; i < total; i += 64) {
             const uint32_t r = i / KC, c = i % KC;
-            yb[r * ldy + c] = OutScale<XT>::apply(from_fixed(acc[lo * KC + i], fexp[c]), yscale, c);
+            const int64_t t = row0 + lo + r;
+            const int64_t yr = rmap ? (int64_t)rmap[t] : t;
+            Y[yr * ldy + c] = OutScale<XT>::apply(from_fixed(acc[lo * KC + i], fexp[c]), yscale, c);
         }
         return;
     }
@@ -383,7 +384,9 @@ __device__ __forceinline__ void process_item(
         unsigned long long s = 0ull;
         for (uint32_t p = cd.part_begin; p < cd.part_end; ++p)
             s += (unsigned long long)__builtin_nontemporal_load(part + (size_t)p * KC + lane);
-        Y[(row0 + cd.row) * ldy + lane] = OutScale<XT>::apply(from_fixed(s, fexp[lane]), yscale, lane);
+        const int64_t t = row0 + cd.row;
+        const int64_t yr = rmap ? (int64_t)rmap[t] : t;
+        Y[yr * ldy + lane] = OutScale<XT>::apply(from_fixed(s, fexp[lane]), yscale, lane);
     }
     if (lane == 0) atomicExch(&count[d.cid], 0u);
 }
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(256) void spmm_items(
     uint64_t blob_bias, const XT* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
     int64_t* __restrict__ part, const CombineDesc* __restrict__ combine,
     uint32_t* __restrict__ count, const float* __restrict__ yscale, const int32_t* __restrict__ fexp,
-    uint32_t h, uint32_t wshift) {
+    const int32_t* __restrict__ rmap, uint32_t h, uint32_t wshift) {
     extern __shared__ unsigned long long lds[];
     const uint32_t waves = blockDim.x >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -404,8 +407,8 @@ __global__ __launch_bounds__(256) void spmm_items(
     unsigned long long* acc = lds + (size_t)wave * h * KC;
     uint32_t* jt = reinterpret_cast<uint32_t*>(lds + (size_t)waves * h * KC) + wave * kJTab;
     const ItemDesc d = items[it];
-    process_item<KC, VW, XT, HV, false>(d, blob, blob_bias, X, ldx, Y, ldy, part, combine, count, yscale, fexp, h,
-                                        wshift, acc, jt, nullptr, 0u, threadIdx.x & 63);
+    process_item<KC, VW, XT, HV, false>(d, blob, blob_bias, X, ldx, Y, ldy, part, combine, count, yscale, fexp, rmap,
+                                        h, wshift, acc, jt, nullptr, 0u, threadIdx.x & 63);
 }
 
 // Persistent variant with X rows staged in LDS: the workgroup first copies
@@ -421,7 +424,7 @@ __global__ __launch_bounds__(1024) void spmm_items_staged(
     uint64_t blob_bias, const XT* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
     int64_t* __restrict__ part, const CombineDesc* __restrict__ combine,
     uint32_t* __restrict__ count, const float* __restrict__ yscale, const int32_t* __restrict__ fexp,
-    uint32_t h, uint32_t wshift, uint32_t ns) {
+    const int32_t* __restrict__ rmap, uint32_t h, uint32_t wshift, uint32_t ns) {
     extern __shared__ unsigned long long lds[];
     float* xs = reinterpret_cast<float*>(lds);
     for (uint32_t t = threadIdx.x; t < ns * KC; t += blockDim.x) {
@@ -438,7 +441,7 @@ __global__ __launch_bounds__(1024) void spmm_items_staged(
     for (uint32_t it = blockIdx.x * waves + wave; it < n_items; it += gridDim.x * waves) {
         const ItemDesc d = items[it];
         process_item<KC, VW, XT, HV, true>(d, blob, blob_bias, X, ldx, Y, ldy, part, combine, count, yscale, fexp,
-                                           h, wshift, acc, jt, xs, ns, threadIdx.x & 63);
+                                           rmap, h, wshift, acc, jt, xs, ns, threadIdx.x & 63);
     }
 }
 
@@ -514,13 +517,13 @@ hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, true>), dim3(grid), dim3(64 * kWaves), bytes,
                                        a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
-                                       H.d_part, a.combine, a.count, yscale, fexp, H.h, H.wshift, (uint32_t)ns);
+                                       H.d_part, a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift, (uint32_t)ns);
                 } else {
                     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, false>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, false>), dim3(grid), dim3(64 * kWaves), bytes,
                                        a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
-                                       H.d_part, a.combine, a.count, yscale, fexp, H.h, H.wshift, (uint32_t)ns);
+                                       H.d_part, a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift, (uint32_t)ns);
                 }
                 return hipGetLastError();
             }
@@ -533,11 +536,11 @@ hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
     if (H.has_val)
         hipLaunchKernelGGL((spmm_items<KC, VW, XT, true>), dim3(grid), dim3(64 * wpb), (size_t)per_wave * wpb,
                            a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part,
-                           a.combine, a.count, yscale, fexp, H.h, H.wshift);
+                           a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift);
     else
         hipLaunchKernelGGL((spmm_items<KC, VW, XT, false>), dim3(grid), dim3(64 * wpb), (size_t)per_wave * wpb,
                            a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part,
-                           a.combine, a.count, yscale, fexp, H.h, H.wshift);
+                           a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift);
     return hipGetLastError();
 }
 
@@ -676,6 +679,24 @@ hipError_t launch_prepare_x(const void* X, int dtype, int64_t ldx, int k, const 
                           s);
     }
     hipLaunchKernelGGL(fexp_kernel, dim3(1), dim3(64), 0, s, colmax, k, row_l1, fexp);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ __launch_bounds__(256) void zero_rows_kernel(float* __restrict__ Y, int64_t ldy, int k,
+                                                        const int32_t* __restrict__ rows, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count * k) return;
+    const int64_t r = i / k;
+    Y[(int64_t)rows[r] * ldy + (i - r * k)] = 0.0f;
+}
+}  // namespace
+
+hipError_t launch_zero_rows(float* Y, int64_t ldy, int k, const int32_t* rows, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t total = count * k;
+    hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Y, ldy, k, rows,
+                       count);
     return hipGetLastError();
 }
 

@@ -123,12 +123,15 @@ def test_tile_stats_match_definition():
     indeg = np.bincount(col, minlength=n)
     rank = np.empty(n, np.int64)
     rank[np.lexsort((np.arange(n), -indeg))] = np.arange(n)   # by (-in-degree, id)
-    for keep, c in ((True, col.astype(np.int64)), (False, rank[col])):
+    outdeg = np.diff(rp)
+    rrank = np.empty(n, np.int64)
+    rrank[np.lexsort((np.arange(n), -outdeg))] = np.arange(n)  # by (-out-degree, id)
+    for keep, r, c in ((True, rows, col.astype(np.int64)), (False, rrank[rows], rank[col])):
         hd = pk.spmm_build_tiles(rp, col, tile_rows=h, tile_cols=w, keep_order=keep)
         st = pk.spmm_get_stats(hd)
-        tiles = (rows // h) * (n // w) + c // w
+        tiles = (r // h) * (n // w) + c // w
         assert st["n_tiles"] == np.unique(tiles).size
-        assert st["sum_nnr"] == np.unique(tiles * n + rows).size
+        assert st["sum_nnr"] == np.unique(tiles * n + r).size
         assert st["sum_nnc"] == np.unique(tiles * n + c).size
         hd.close()
 
@@ -211,3 +214,22 @@ def test_transposed_build_checks_input():
     with pytest.raises(pk.SpmmError) as ei:
         pk.spmm_build_tiles(rp, bad, transpose=True)
     assert ei.value.status == pk.SPMM_EINVAL
+
+
+def test_row_order_by_degree_and_empty_rows_untiled():
+    """Default build: tile rows take the rows by descending out-degree and
+    rows without entries are not tiled (they are zero-filled at run time);
+    keep_row_order (or keep_order) tiles every row in the given order.  Both
+    decode back to the input CSR."""
+    rp, col = synth.rmat_csr(13, 4, seed=3)
+    n = rp.shape[0] - 1
+    live = int(np.count_nonzero(np.diff(rp)))
+    assert live < n
+    h = 32
+    for opts, slabs in ((dict(), -(-live // h)), (dict(keep_row_order=True), -(-n // h)),
+                        (dict(keep_order=True), -(-n // h))):
+        hd = pk.spmm_build_tiles(rp, col, tile_rows=h, **opts)
+        assert pk.spmm_get_stats(hd)["n_slabs"] == slabs, opts
+        drp, dcol = pk.spmm_decode_tiles(hd, col.shape[0])
+        assert np.array_equal(drp, rp) and np.array_equal(dcol, col), opts
+        hd.close()
