@@ -149,6 +149,48 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
                                const int32_t* col_idx, const float* values,
                                const spmm_build_opts* opts, spmm_handle_t* out);
 
+/*
+ * Slab-wise build, for a matrix whose CSR is produced (or held) a block of
+ * rows at a time: the same tile store as spmm_build_tiles, without the whole
+ * CSR in host memory at once.  The conversion is still one linear pass over
+ * the rows (Section 3.2; the conversion cost of Section 5, Table 3).
+ *
+ * spmm_build_begin: a handle for an n_rows x n_cols matrix, to be filled by
+ *   spmm_build_append_rows and completed by spmm_build_end.  Options as for
+ *   spmm_build_tiles, except that
+ *     - the columns keep the given order (the in-degree order needs every
+ *       column's count before the first tile is cut): order the columns
+ *       beforehand if hub columns should be contiguous;
+ *     - rows are taken by descending out-degree within each appended block
+ *       (together with the rows still untiled from the block before), unless
+ *       keep_row_order or keep_order is set;
+ *     - transpose is not supported (SPMM_EUNSUPPORTED).
+ *   Errors: SPMM_EINVAL (shape, options), SPMM_EUNSUPPORTED, SPMM_ENOMEM.
+ *
+ * spmm_build_append_rows: rows [row0, row0 + nrows), in order: row0 must be
+ *   the first row not yet appended.
+ *     row_ptr_local : host int64[nrows + 1], row_ptr_local[0] = 0; row i's
+ *                     entries are col_idx[row_ptr_local[i - row0] ..].
+ *     col_idx       : host int32, columns sorted ascending without
+ *                     duplicates within a row (checked if opts->validate).
+ *     values        : host float or NULL; NULL for every block or for none
+ *                     (the first call decides).
+ *   The arrays are read during the call only; the caller may free them on
+ *   return.  Whole tile rows are tiled at once; up to tile_rows - 1 rows are
+ *   copied and kept for the next call.  On error the handle must be
+ *   destroyed.  Errors: SPMM_EINVAL (order, CSR), SPMM_ESTATE (not being
+ *   built), SPMM_ENOMEM.
+ *
+ * spmm_build_end: tiles the rows still kept and encodes the work items; the
+ *   handle can then be used like one from spmm_build_tiles.  Every other
+ *   entry point rejects a handle between begin and end with SPMM_ESTATE.
+ *   Errors: SPMM_ESTATE (rows missing, or not being built), SPMM_ENOMEM.
+ */
+spmm_status_t spmm_build_begin(int64_t n_rows, int64_t n_cols, const spmm_build_opts* opts, spmm_handle_t* out);
+spmm_status_t spmm_build_append_rows(spmm_handle_t h, int64_t row0, int64_t nrows, const int64_t* row_ptr_local,
+                                     const int32_t* col_idx, const float* values);
+spmm_status_t spmm_build_end(spmm_handle_t h);
+
 /* Release a handle and everything it owns.  NULL is ignored.  Waits for
    work already enqueued on the handle's device buffers to finish. */
 void spmm_destroy(spmm_handle_t h);

@@ -120,6 +120,12 @@ def load_library():
     L.spmm_build_tiles.restype = i32
     L.spmm_build_tiles.argtypes = [i64, i64, vp, vp, vp, ctypes.POINTER(spmm_build_opts),
                                    ctypes.POINTER(vp)]
+    L.spmm_build_begin.restype = i32
+    L.spmm_build_begin.argtypes = [i64, i64, ctypes.POINTER(spmm_build_opts), ctypes.POINTER(vp)]
+    L.spmm_build_append_rows.restype = i32
+    L.spmm_build_append_rows.argtypes = [vp, i64, i64, vp, vp, vp]
+    L.spmm_build_end.restype = i32
+    L.spmm_build_end.argtypes = [vp]
     L.spmm_destroy.restype = None
     L.spmm_destroy.argtypes = [vp]
     L.spmm_run.restype = i32
@@ -255,6 +261,43 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
                             None if va is None else va.ctypes.data, ctypes.byref(o), ctypes.byref(out))
     _check(st, "spmm_build_tiles")
     return Handle(out.value, n_cols, n_rows) if transpose else Handle(out.value, n_rows, n_cols)
+
+
+def _opts(tile_rows=0, tile_cols=0, fixed_variant=-1, item_nnz=0, place=SPMM_PLACE_DEVICE, threads=0,
+          validate=True, max_kc=0, keep_order=False, stream_kib=0, ring_depth=0, x_stage_kib=0,
+          transpose=False, keep_row_order=False):
+    return spmm_build_opts(tile_rows, tile_cols, fixed_variant, item_nnz, place, threads, int(bool(validate)),
+                           max_kc, int(bool(keep_order)), stream_kib, ring_depth, int(x_stage_kib),
+                           int(bool(transpose)), int(bool(keep_row_order)))
+
+
+def spmm_build_begin(n_rows: int, n_cols: int | None = None, **opts) -> Handle:
+    """Start a slab-wise build (options as spmm_build_tiles; columns keep
+    their order, rows are ordered within each appended block)."""
+    L = load_library()
+    n_cols = n_rows if n_cols is None else int(n_cols)
+    o = _opts(**opts)
+    out = ctypes.c_void_p()
+    _check(L.spmm_build_begin(int(n_rows), n_cols, ctypes.byref(o), ctypes.byref(out)), "spmm_build_begin")
+    return Handle(out.value, int(n_rows), n_cols)
+
+
+def spmm_build_append_rows(h: Handle, row0: int, row_ptr_local, col_idx, values=None) -> None:
+    """Append rows [row0, row0 + len(row_ptr_local) - 1) (local row pointers
+    starting at 0)."""
+    L = load_library()
+    rp = _host(row_ptr_local, np.int64)
+    ci = _host(col_idx, np.int32)
+    va = _host(values, np.float32)
+    nrows = rp.shape[0] - 1
+    st = L.spmm_build_append_rows(h.ptr, int(row0), nrows, rp.ctypes.data,
+                                  None if ci is None or ci.size == 0 else ci.ctypes.data,
+                                  None if va is None else va.ctypes.data)
+    _check(st, "spmm_build_append_rows")
+
+
+def spmm_build_end(h: Handle) -> None:
+    _check(load_library().spmm_build_end(h.ptr), "spmm_build_end")
 
 
 def spmm_destroy(h: Handle):

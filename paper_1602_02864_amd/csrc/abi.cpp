@@ -121,7 +121,14 @@ spmm_status_t upload(spmm::Handle& H) {
     return SPMM_OK;
 }
 
+spmm_status_t check_ready(spmm_handle_t h) {
+    if (!h) return fail(SPMM_EINVAL, "handle is NULL");
+    if (h->H.building) return fail(SPMM_ESTATE, "the handle is still being built (call spmm_build_end)");
+    return SPMM_OK;
+}
+
 spmm_status_t ensure_uploaded(spmm::Handle& H) {
+    if (H.building) return fail(SPMM_ESTATE, "the handle is still being built (call spmm_build_end)");
     if (H.uploaded) return SPMM_OK;
     spmm_status_t st = upload(H);
     if (st != SPMM_OK) free_device(H);
@@ -277,6 +284,42 @@ spmm_status_t launch_items_only(spmm::Handle& H, const void* X, int k, int64_t l
     return e == hipSuccess ? SPMM_OK : hip_fail(e, "kernel launch");
 }
 
+// Defaults and range checks of the build options.
+spmm_status_t parse_opts(const spmm_build_opts* opts, spmm_build_opts& o) {
+    o = spmm_build_opts{};
+    if (opts) o = *opts;
+    if (o.max_kc == 0) o.max_kc = 32;
+    if (o.max_kc != 16 && o.max_kc != 32) return fail(SPMM_EINVAL, "max_kc must be 16 or 32");
+    if (o.tile_rows == 0) o.tile_rows = spmm::kDefaultTileRows;
+    if (o.tile_cols == 0) o.tile_cols = spmm::kDefaultTileCols;
+    if (o.item_nnz == 0) o.item_nnz = spmm::kDefaultItemNnz;
+    if (o.tile_rows > spmm::kMaxTileRows) return fail(SPMM_EINVAL, "tile_rows must be <= 4096");
+    if (o.item_nnz > spmm::kMaxItemNnz) return fail(SPMM_EINVAL, "item_nnz must be <= 131072");
+    if (!is_pow2(o.tile_cols) || o.tile_cols > 65536) return fail(SPMM_EINVAL, "tile_cols must be a power of two <= 65536");
+    if (o.fixed_variant >= SPMM_NUM_VARIANTS) return fail(SPMM_EINVAL, "unknown variant");
+    if (o.place != SPMM_PLACE_DEVICE && o.place != SPMM_PLACE_PINNED_HOST) return fail(SPMM_EINVAL, "unknown placement");
+    if (o.transpose > 1) return fail(SPMM_EINVAL, "transpose must be 0 or 1");
+    const uint32_t ring = o.ring_depth ? o.ring_depth : 3u;
+    if (ring < 2 || ring > 16) return fail(SPMM_EINVAL, "ring_depth must be in 2..16");
+    return SPMM_OK;
+}
+
+void init_handle(spmm::Handle& H, int64_t n_rows, int64_t n_cols, const spmm_build_opts& o) {
+    H.n_rows = n_rows;
+    H.n_cols = n_cols;
+    H.h = o.tile_rows;
+    H.w = o.tile_cols;
+    H.item_nnz = o.item_nnz;
+    H.threads = o.threads;
+    H.place = o.place;
+    H.max_kc = (int)o.max_kc;
+    H.relabel = o.keep_order == 0;
+    H.row_relabel = o.keep_order == 0 && o.keep_row_order == 0;
+    H.stream_bytes = (uint64_t)(o.stream_kib ? o.stream_kib : 262144u) << 10;
+    H.ring_depth = o.ring_depth ? o.ring_depth : 3u;
+    H.stage_bytes = o.x_stage_kib > 0 ? (uint64_t)o.x_stage_kib << 10 : 0u;
+}
+
 }  // namespace spmm_abi
 
 using namespace spmm_abi;
@@ -295,20 +338,8 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         if (!row_ptr) return fail(SPMM_EINVAL, "row_ptr is NULL");
         if (row_ptr[n_rows] > 0 && !col_idx) return fail(SPMM_EINVAL, "col_idx is NULL");
         spmm_build_opts o{};
-        if (opts) o = *opts;
-        if (o.max_kc == 0) o.max_kc = 32;
-        if (o.max_kc != 16 && o.max_kc != 32) return fail(SPMM_EINVAL, "max_kc must be 16 or 32");
-        if (o.tile_rows == 0) o.tile_rows = spmm::kDefaultTileRows;
-        if (o.tile_cols == 0) o.tile_cols = spmm::kDefaultTileCols;
-        if (o.item_nnz == 0) o.item_nnz = spmm::kDefaultItemNnz;
-        if (o.tile_rows > spmm::kMaxTileRows) return fail(SPMM_EINVAL, "tile_rows must be <= 4096");
-        if (o.item_nnz > spmm::kMaxItemNnz) return fail(SPMM_EINVAL, "item_nnz must be <= 131072");
-        if (!is_pow2(o.tile_cols) || o.tile_cols > 65536)
-            return fail(SPMM_EINVAL, "tile_cols must be a power of two <= 65536");
-        if (o.fixed_variant >= SPMM_NUM_VARIANTS) return fail(SPMM_EINVAL, "unknown variant");
-        if (o.place != SPMM_PLACE_DEVICE && o.place != SPMM_PLACE_PINNED_HOST)
-            return fail(SPMM_EINVAL, "unknown placement");
-        if (o.transpose > 1) return fail(SPMM_EINVAL, "transpose must be 0 or 1");
+        spmm_status_t st = parse_opts(opts, o);
+        if (st != SPMM_OK) return st;
         // with transpose, tile the CSR of A^T instead (rows and columns swap)
         std::vector<int64_t> t_ptr;
         std::vector<int32_t> t_col;
@@ -325,22 +356,9 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         }
         std::unique_ptr<spmm_handle_s> hs(new spmm_handle_s);
         spmm::Handle& H = hs->H;
-        H.n_rows = n_rows;
-        H.n_cols = n_cols;
-        H.h = o.tile_rows;
-        H.w = o.tile_cols;
-        H.item_nnz = o.item_nnz;
-        H.threads = o.threads;
-        H.place = o.place;
-        H.max_kc = (int)o.max_kc;
-        H.relabel = o.keep_order == 0;
-        H.row_relabel = o.keep_order == 0 && o.keep_row_order == 0;
-        H.stream_bytes = (uint64_t)(o.stream_kib ? o.stream_kib : 262144u) << 10;
-        H.ring_depth = o.ring_depth ? o.ring_depth : 3u;
-        H.stage_bytes = o.x_stage_kib > 0 ? (uint64_t)o.x_stage_kib << 10 : 0u;
-        if (H.ring_depth < 2 || H.ring_depth > 16) return fail(SPMM_EINVAL, "ring_depth must be in 2..16");
+        init_handle(H, n_rows, n_cols, o);
         std::string err;
-        spmm_status_t st = spmm::build_canonical(H, row_ptr, col_idx, values, o.validate != 0, err);
+        st = spmm::build_canonical(H, row_ptr, col_idx, values, o.validate != 0, err);
         if (st != SPMM_OK) return fail(st, err);
         if (o.fixed_variant >= 0) std::fill(H.variant.begin(), H.variant.end(), (uint8_t)o.fixed_variant);
         st = spmm::encode(H, err);
@@ -351,6 +369,73 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         return fail(SPMM_ENOMEM, "out of host memory");
     } catch (const std::exception& e) {
         return fail(SPMM_EINVAL, e.what());
+    }
+}
+
+spmm_status_t spmm_build_begin(int64_t n_rows, int64_t n_cols, const spmm_build_opts* opts, spmm_handle_t* out) {
+    try {
+        if (!out) return fail(SPMM_EINVAL, "out is NULL");
+        if (n_rows < 0 || n_cols < 0 || n_rows > INT32_MAX || n_cols > INT32_MAX)
+            return fail(SPMM_EINVAL, "n_rows and n_cols must be in 0..2^31-1");
+        spmm_build_opts o{};
+        spmm_status_t st = parse_opts(opts, o);
+        if (st != SPMM_OK) return st;
+        if (o.transpose) return fail(SPMM_EUNSUPPORTED, "a slab-wise build cannot transpose; build A^T's rows instead");
+        std::unique_ptr<spmm_handle_s> hs(new spmm_handle_s);
+        spmm::Handle& H = hs->H;
+        init_handle(H, n_rows, n_cols, o);
+        // the column order would need every column's in-degree before the
+        // first tile: a slab-wise build keeps the given column order
+        H.relabel = false;
+        H.building = true;
+        H.validate_rows = o.validate != 0;
+        H.fixed_variant = o.fixed_variant;
+        spmm::build_init(H, false);
+        H.has_val_known = false;
+        *out = hs.release();
+        return SPMM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SPMM_ENOMEM, "out of host memory");
+    }
+}
+
+spmm_status_t spmm_build_append_rows(spmm_handle_t h, int64_t row0, int64_t nrows, const int64_t* row_ptr_local,
+                                     const int32_t* col_idx, const float* values) {
+    try {
+        if (!h || !row_ptr_local) return fail(SPMM_EINVAL, "NULL argument");
+        spmm::Handle& H = h->H;
+        if (!H.building) return fail(SPMM_ESTATE, "the handle is not being built (spmm_build_begin)");
+        if (nrows < 0) return fail(SPMM_EINVAL, "nrows must be >= 0");
+        if (row_ptr_local[nrows] > 0 && !col_idx) return fail(SPMM_EINVAL, "col_idx is NULL");
+        if (!H.has_val_known) {
+            H.has_val = values != nullptr;
+            H.has_val_known = true;
+        }
+        std::string err;
+        spmm_status_t st = spmm::build_append(H, row0, nrows, row_ptr_local, col_idx, values, H.validate_rows, err);
+        return st == SPMM_OK ? st : fail(st, err);
+    } catch (const std::bad_alloc&) {
+        return fail(SPMM_ENOMEM, "out of host memory");
+    }
+}
+
+spmm_status_t spmm_build_end(spmm_handle_t h) {
+    try {
+        if (!h) return fail(SPMM_EINVAL, "handle is NULL");
+        spmm::Handle& H = h->H;
+        if (!H.building) return fail(SPMM_ESTATE, "the handle is not being built (spmm_build_begin)");
+        if (H.next_row != H.n_rows)
+            return fail(SPMM_ESTATE, "rows " + std::to_string(H.next_row) + ".." + std::to_string(H.n_rows) +
+                                         " have not been appended");
+        std::string err;
+        spmm_status_t st = spmm::build_finish_rows(H, err);
+        if (st != SPMM_OK) return fail(st, err);
+        if (H.fixed_variant >= 0) std::fill(H.variant.begin(), H.variant.end(), (uint8_t)H.fixed_variant);
+        if ((st = spmm::encode(H, err)) != SPMM_OK) return fail(st, err);
+        H.building = false;
+        return SPMM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SPMM_ENOMEM, "out of host memory");
     }
 }
 
@@ -710,6 +795,7 @@ spmm_status_t spmm_read_probe(const void* buf, uint64_t bytes, float* sink, hipS
 }
 
 spmm_status_t spmm_timing_begin(spmm_handle_t h) {
+    if (spmm_status_t rs = check_ready(h)) return rs;
     if (!h) return fail(SPMM_EINVAL, "handle is NULL");
     h->H.timing = true;
     h->H.timing_used = 0;
@@ -736,6 +822,7 @@ spmm_status_t spmm_timing_end(spmm_handle_t h, double* total_ms, uint64_t* n_run
 }
 
 spmm_status_t spmm_get_stats(spmm_handle_t h, spmm_stats_t* out) {
+    if (spmm_status_t rs = check_ready(h)) return rs;
     if (!h || !out) return fail(SPMM_EINVAL, "NULL argument");
     const spmm::Handle& H = h->H;
     spmm_stats_t s{};
@@ -762,6 +849,7 @@ spmm_status_t spmm_get_stats(spmm_handle_t h, spmm_stats_t* out) {
 
 spmm_status_t spmm_decode_tiles(spmm_handle_t h, int64_t* row_ptr, int32_t* col_idx, float* values) {
     try {
+        if (spmm_status_t rs = check_ready(h)) return rs;
         if (!h || !row_ptr || (h->H.nnz > 0 && !col_idx)) return fail(SPMM_EINVAL, "NULL argument");
         if (values && !h->H.has_val) return fail(SPMM_EINVAL, "the matrix is binary; pass values = NULL");
         std::string err;

@@ -20,6 +20,10 @@ namespace spmm_abi {
 spmm_status_t fail(spmm_status_t st, const std::string& msg);
 spmm_status_t hip_fail(hipError_t e, const char* what);
 
+// SPMM_EINVAL for a NULL handle, SPMM_ESTATE for one whose slab-wise build
+// has not ended, else SPMM_OK.
+spmm_status_t check_ready(spmm_handle_t h);
+
 // Release every device and pinned buffer of H; H.uploaded becomes false.
 void free_device(spmm::Handle& H);
 // Upload the encoded work (once) and size the split-row partial slots.

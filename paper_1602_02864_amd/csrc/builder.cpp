@@ -106,165 +106,78 @@ spmm_status_t transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t* row_p
     return SPMM_OK;
 }
 
-spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* col,
-                              const float* val, bool validate, std::string& err) {
-    const int64_t n = H.n_rows;
-    if (row_ptr[0] != 0) {
-        err = "row_ptr[0] must be 0";
-        return SPMM_EINVAL;
-    }
-    const int64_t nnz = row_ptr[n];
-    if (nnz < 0) {
-        err = "row_ptr[n_rows] is negative";
-        return SPMM_EINVAL;
-    }
-    H.nnz = nnz;
-    H.has_val = val != nullptr;
-    H.wshift = log2_exact(H.w);
-    H.n_strips = (uint64_t)((H.n_cols + H.w - 1) / H.w);
-    if (H.n_strips == 0) H.n_strips = 1;
+namespace {
 
-    // Row pointers must be monotone; columns in range (and sorted, unique when
-    // validation is on: the tile encoding relies on sorted rows only for
-    // determinism of the layout, not for correctness).
-    std::atomic<int> bad{0};
-    parallel_for((uint64_t)n, H.threads, 1 << 16, [&](uint64_t a, uint64_t b) {
-        for (uint64_t i = a; i < b; ++i) {
-            if (row_ptr[i + 1] < row_ptr[i]) { bad = 1; return; }
-            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
-                if (col[p] < 0 || col[p] >= H.n_cols) { bad = 2; return; }
-                if (validate && p > row_ptr[i] && col[p] <= col[p - 1]) { bad = 3; return; }
-            }
-        }
-    });
-    if (bad) {
-        err = bad == 1 ? "row_ptr is not non-decreasing"
-            : bad == 2 ? "column index out of range"
-                       : "columns not sorted and unique within a row";
-        return SPMM_EINVAL;
-    }
+// One row to tile: its original id and its entries.
+struct RowRef {
+    int64_t row;
+    const int32_t* col;
+    const float* val;
+    uint64_t len;
+};
 
-    // largest row L1 norm (bounds every partial sum of a row)
-    {
-        std::atomic<uint64_t> best{0};
-        parallel_for((uint64_t)n, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
-            double m = 0.0;
-            for (uint64_t i = a; i < b; ++i) {
-                double r = 0.0;
-                if (val)
-                    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) r += std::fabs((double)val[p]);
-                else
-                    r = (double)(row_ptr[i + 1] - row_ptr[i]);
-                m = std::max(m, r);
-            }
-            uint64_t bits;
-            std::memcpy(&bits, &m, 8);
-            uint64_t cur = best.load();
-            while (bits > cur && !best.compare_exchange_weak(cur, bits)) {}
-        });
-        uint64_t bits = best.load();
-        std::memcpy(&H.max_row_l1, &bits, 8);
-        if (!std::isfinite(H.max_row_l1)) {
-            err = "values must be finite";
-            return SPMM_EINVAL;
-        }
+// Append `rows` (in tile order) to H as new tile rows of h rows each; every
+// tile row must be full except the last of the whole matrix.  Columns pass
+// through H's column map.  The tile store grows by the rows' entries, tile
+// major, sorted by (local row, local column) within each tile.
+spmm_status_t tile_rows(Handle& H, const RowRef* rows, int64_t count, std::string& err) {
+    if (count <= 0) return SPMM_OK;
+    if (H.n_tiled_rows % H.h) {
+        err = "internal: a partial tile row is not last";
+        return SPMM_ESTATE;
     }
-
-    // Column relabelling by descending in-degree (ties by column id): a
-    // counting sort over degrees, stable in the original order.
-    const int32_t* cmap = nullptr;
-    H.col_count.assign((size_t)H.n_cols, 0);
-    std::vector<uint32_t>& indeg = H.col_count;
-    parallel_for((uint64_t)n, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
-        for (int64_t p = row_ptr[a]; p < row_ptr[b]; ++p)
-            __atomic_fetch_add(&indeg[col[p]], 1u, __ATOMIC_RELAXED);
-    });
-    if (H.relabel) {
-        const int64_t m = H.n_cols;
-        uint32_t maxd = 0;
-        for (int64_t c = 0; c < m; ++c) maxd = std::max(maxd, indeg[c]);
-        std::vector<uint64_t> start((size_t)maxd + 2, 0);
-        for (int64_t c = 0; c < m; ++c) start[maxd - indeg[c] + 1]++;
-        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
-        H.col_new.resize((size_t)m);
-        H.col_old.resize((size_t)m);
-        for (int64_t c = 0; c < m; ++c) {
-            const uint64_t r = start[maxd - indeg[c]]++;
-            H.col_new[c] = (int32_t)r;
-            H.col_old[r] = (int32_t)c;
-        }
-        cmap = H.col_new.data();
-    }
+    const int32_t* cmap = H.relabel ? H.col_new.data() : nullptr;
     auto colmap = [cmap](int32_t c) -> uint32_t { return cmap ? (uint32_t)cmap[c] : (uint32_t)c; };
-
-    // Row order.  With row relabelling, tile rows take the rows in order of
-    // descending out-degree (ties by row id), so that rows sharing the hub
-    // columns sit in the same tile rows and their X rows are gathered once
-    // per tile row; rows without entries come last and are not tiled (their
-    // Y rows are zero-filled).  rp_new is the prefix of row lengths in the
-    // tile order: the entries of tile row s start at rp_new[s * h] in ent.
-    H.row_old.clear();
-    H.n_tiled_rows = n;
-    std::vector<int64_t> rp_new;
-    if (H.row_relabel && n > 0) {
-        uint64_t maxd = 0;
-        for (int64_t r = 0; r < n; ++r) maxd = std::max<uint64_t>(maxd, (uint64_t)(row_ptr[r + 1] - row_ptr[r]));
-        // counting sort on key = cap - min(degree, cap) (descending degree,
-        // stable in row id); rows of degree >= cap share key 0 and are then
-        // ordered exactly
-        const uint64_t cap = std::min<uint64_t>(maxd, 1u << 20);
-        auto key = [&](int64_t r) -> uint64_t {
-            return cap - std::min<uint64_t>(cap, (uint64_t)(row_ptr[r + 1] - row_ptr[r]));
-        };
-        std::vector<uint64_t> start(cap + 2, 0);
-        for (int64_t r = 0; r < n; ++r) start[key(r) + 1]++;
-        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
-        const uint64_t nbig = start[1];
-        H.row_old.resize((size_t)n);
-        for (int64_t r = 0; r < n; ++r) H.row_old[start[key(r)]++] = (int32_t)r;
-        std::stable_sort(H.row_old.begin(), H.row_old.begin() + (int64_t)nbig, [&](int32_t x, int32_t y) {
-            return row_ptr[x + 1] - row_ptr[x] > row_ptr[y + 1] - row_ptr[y];
-        });
-        int64_t live = n;
-        while (live > 0 && row_ptr[H.row_old[live - 1] + 1] == row_ptr[H.row_old[live - 1]]) --live;
-        H.n_tiled_rows = live;
-        rp_new.resize((size_t)live + 1);
-        rp_new[0] = 0;
-        for (int64_t r = 0; r < live; ++r) rp_new[r + 1] = rp_new[r] + (row_ptr[H.row_old[r] + 1] - row_ptr[H.row_old[r]]);
+    const bool hv = H.has_val;
+    const uint64_t s_first = H.n_slabs;
+    const uint64_t ns = (uint64_t)((count + H.h - 1) / H.h);
+    // entry offset of each new slab within the block
+    std::vector<uint64_t> sbase(ns + 1, 0);
+    for (uint64_t s = 0; s < ns; ++s) {
+        uint64_t e = 0;
+        const int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(count, r0 + H.h);
+        for (int64_t r = r0; r < r1; ++r) e += rows[r].len;
+        sbase[s + 1] = sbase[s] + e;
     }
-    const int32_t* rmap = H.row_old.empty() ? nullptr : H.row_old.data();
-    auto row_begin = [&](int64_t r) -> int64_t { return rmap ? row_ptr[rmap[r]] : row_ptr[r]; };
-    auto row_end = [&](int64_t r) -> int64_t { return rmap ? row_ptr[rmap[r] + 1] : row_ptr[r + 1]; };
-    auto tiled_base = [&](int64_t r) -> int64_t { return rmap ? rp_new[r] : row_ptr[r]; };
-    const int64_t nt = H.n_tiled_rows;
-    H.n_slabs = (uint64_t)((nt + H.h - 1) / H.h);
+    const uint64_t ent0 = H.ent.size(), bnnz = sbase[ns];
 
-    // Pass 1: non-empty tiles per slab.
-    std::vector<uint64_t> ntile(H.n_slabs + 1, 0);
+    // Pass 1: non-empty tiles per new slab.
+    std::vector<uint64_t> ntile(ns + 1, 0);
     const uint32_t nstrip = (uint32_t)H.n_strips;
-    parallel_for(H.n_slabs, H.threads, 64, [&](uint64_t a, uint64_t b) {
+    parallel_for(ns, H.threads, 64, [&](uint64_t a, uint64_t b) {
         std::vector<uint32_t> cnt(nstrip, 0);
         std::vector<uint32_t> used;
         for (uint64_t s = a; s < b; ++s) {
-            int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(nt, r0 + H.h);
+            const int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(count, r0 + H.h);
             used.clear();
             for (int64_t r = r0; r < r1; ++r)
-                for (int64_t p = row_begin(r); p < row_end(r); ++p) {
-                    uint32_t J = colmap(col[p]) >> H.wshift;
+                for (uint64_t p = 0; p < rows[r].len; ++p) {
+                    const uint32_t J = colmap(rows[r].col[p]) >> H.wshift;
                     if (cnt[J]++ == 0) used.push_back(J);
                 }
             ntile[s + 1] = used.size();
             for (uint32_t J : used) cnt[J] = 0;
         }
     });
-    H.slab_tiles.assign(H.n_slabs + 1, 0);
-    for (uint64_t s = 0; s < H.n_slabs; ++s) H.slab_tiles[s + 1] = H.slab_tiles[s] + ntile[s + 1];
-    const uint64_t T = H.slab_tiles[H.n_slabs];
+    const uint64_t t_first = H.tiles.size();
+    if (H.slab_tiles.empty()) H.slab_tiles.push_back(0);
+    for (uint64_t s = 0; s < ns; ++s) H.slab_tiles.push_back(H.slab_tiles.back() + ntile[s + 1]);
+    const uint64_t T = H.slab_tiles.back();
     try {
+        // grow by at least a quarter, so that a build in many blocks does
+        // not reallocate per block (and never doubles its peak footprint)
+        auto grow = [](auto& v, size_t need) {
+            if (need > v.capacity()) v.reserve(std::max(need, v.capacity() + v.capacity() / 4));
+            v.resize(need);
+        };
         H.tiles.resize(T);
-        H.ent.resize((size_t)nnz);
-        if (val) H.val.resize((size_t)nnz);
-        H.variant.assign(T, (uint8_t)SPMM_VAR_HYBRID);
+        grow(H.ent, ent0 + bnnz);
+        if (hv) grow(H.val, ent0 + bnnz);
+        H.variant.resize(T, (uint8_t)SPMM_VAR_HYBRID);
+        if (H.row_relabel) {
+            grow(H.row_old, (size_t)(H.n_tiled_rows + count));
+            for (int64_t r = 0; r < count; ++r) H.row_old[(size_t)(H.n_tiled_rows + r)] = (int32_t)rows[r].row;
+        }
     } catch (const std::bad_alloc&) {
         err = "out of host memory for the tile store";
         return SPMM_ENOMEM;
@@ -272,27 +185,28 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
 
     // Pass 2: scatter entries tile-major, then per-tile statistics.
     std::atomic<uint64_t> tot_nnr{0}, tot_nnc{0};
-    parallel_for(H.n_slabs, H.threads, 64, [&](uint64_t a, uint64_t b) {
+    parallel_for(ns, H.threads, 64, [&](uint64_t a, uint64_t b) {
         std::vector<uint32_t> cnt(nstrip, 0);
         std::vector<uint64_t> pos(nstrip, 0);
         std::vector<uint32_t> used;
         std::vector<uint64_t> seen((H.w + 63) / 64, 0);
         uint64_t my_nnr = 0, my_nnc = 0;
         for (uint64_t s = a; s < b; ++s) {
-            int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(nt, r0 + H.h);
+            const int64_t r0 = (int64_t)s * H.h, r1 = std::min<int64_t>(count, r0 + H.h);
+            const uint64_t gs = s_first + s;
             used.clear();
             for (int64_t r = r0; r < r1; ++r)
-                for (int64_t p = row_begin(r); p < row_end(r); ++p) {
-                    uint32_t J = colmap(col[p]) >> H.wshift;
+                for (uint64_t p = 0; p < rows[r].len; ++p) {
+                    const uint32_t J = colmap(rows[r].col[p]) >> H.wshift;
                     if (cnt[J]++ == 0) used.push_back(J);
                 }
             std::sort(used.begin(), used.end());
-            uint64_t e = (uint64_t)tiled_base(r0);
-            uint64_t t = H.slab_tiles[s];
+            uint64_t e = ent0 + sbase[s];
+            uint64_t t = H.slab_tiles[gs];
             for (uint32_t J : used) {
                 Tile& tl = H.tiles[t++];
                 tl.ent_begin = e;
-                tl.slab = (uint32_t)s;
+                tl.slab = (uint32_t)gs;
                 tl.J = J;
                 tl.nnz = cnt[J];
                 pos[J] = e;
@@ -300,21 +214,21 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
                 cnt[J] = 0;
             }
             for (int64_t r = r0; r < r1; ++r) {
-                uint32_t rl = (uint32_t)(r - r0);
-                for (int64_t p = row_begin(r); p < row_end(r); ++p) {
-                    uint32_t c = colmap(col[p]);
-                    uint64_t q = pos[c >> H.wshift]++;
+                const uint32_t rl = (uint32_t)(r - r0);
+                for (uint64_t p = 0; p < rows[r].len; ++p) {
+                    const uint32_t c = colmap(rows[r].col[p]);
+                    const uint64_t q = pos[c >> H.wshift]++;
                     H.ent[q] = (rl << 16) | (c & (H.w - 1));
-                    if (val) H.val[q] = val[p];
+                    if (hv) H.val[q] = rows[r].val[p];
                 }
             }
             if (cmap) {
                 // relabelled columns arrive unordered within a row: sort each
                 // tile's entries by (row, column), carrying the values along
-                for (uint64_t ti = H.slab_tiles[s]; ti < H.slab_tiles[s + 1]; ++ti) {
+                for (uint64_t ti = H.slab_tiles[gs]; ti < H.slab_tiles[gs + 1]; ++ti) {
                     const Tile& tl = H.tiles[ti];
                     uint32_t* E = H.ent.data() + tl.ent_begin;
-                    if (!val) {
+                    if (!hv) {
                         std::sort(E, E + tl.nnz);
                     } else {
                         std::vector<std::pair<uint32_t, float>> tmp(tl.nnz);
@@ -328,7 +242,7 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
                     }
                 }
             }
-            for (uint64_t ti = H.slab_tiles[s]; ti < H.slab_tiles[s + 1]; ++ti) {
+            for (uint64_t ti = H.slab_tiles[gs]; ti < H.slab_tiles[gs + 1]; ++ti) {
                 Tile& tl = H.tiles[ti];
                 const uint32_t* E = H.ent.data() + tl.ent_begin;
                 uint32_t nnr = 0, maxr = 0, single = 0, run = 0, nnc = 0;
@@ -339,8 +253,8 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
                         run = 0;
                     }
                     ++run;
-                    uint32_t c = E[i] & 0xFFFFu;
-                    uint64_t bit = 1ull << (c & 63);
+                    const uint32_t c = E[i] & 0xFFFFu;
+                    const uint64_t bit = 1ull << (c & 63);
                     if (!(seen[c >> 6] & bit)) { seen[c >> 6] |= bit; ++nnc; }
                 }
                 maxr = std::max(maxr, run);
@@ -357,8 +271,232 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
         tot_nnr += my_nnr;
         tot_nnc += my_nnc;
     });
-    H.sum_nnr = tot_nnr;
-    H.sum_nnc = tot_nnc;
+    (void)t_first;
+    H.sum_nnr += tot_nnr;
+    H.sum_nnc += tot_nnc;
+    H.n_slabs += ns;
+    H.n_tiled_rows += count;
+    return SPMM_OK;
+}
+
+// Checks and statistics of nr CSR rows (row_ptr relative to col/val):
+// monotone row pointers, columns in range (sorted and unique when validate),
+// finite values; the largest row L1 norm and the per-column entry counts of
+// H are updated.
+spmm_status_t scan_rows(Handle& H, int64_t nr, const int64_t* rp, const int32_t* col, const float* val,
+                        bool validate, std::string& err) {
+    std::atomic<int> bad{0};
+    std::atomic<uint64_t> best{0};
+    {
+        double cur = H.max_row_l1;
+        uint64_t bits;
+        std::memcpy(&bits, &cur, 8);
+        best = bits;
+    }
+    parallel_for((uint64_t)nr, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
+        double m = 0.0;
+        for (uint64_t i = a; i < b; ++i) {
+            if (rp[i + 1] < rp[i]) { bad = 1; return; }
+            double r = 0.0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                if (col[p] < 0 || col[p] >= H.n_cols) { bad = 2; return; }
+                if (validate && p > rp[i] && col[p] <= col[p - 1]) { bad = 3; return; }
+                if (val) r += std::fabs((double)val[p]);
+            }
+            if (!val) r = (double)(rp[i + 1] - rp[i]);
+            m = std::max(m, r);
+        }
+        if (!std::isfinite(m)) { bad = 4; return; }
+        uint64_t bits;
+        std::memcpy(&bits, &m, 8);
+        uint64_t cur = best.load();
+        while (bits > cur && !best.compare_exchange_weak(cur, bits)) {}
+    });
+    if (bad) {
+        err = bad == 1 ? "row_ptr is not non-decreasing"
+            : bad == 2 ? "column index out of range"
+            : bad == 3 ? "columns not sorted and unique within a row"
+                       : "values must be finite";
+        return SPMM_EINVAL;
+    }
+    const uint64_t bits = best.load();
+    std::memcpy(&H.max_row_l1, &bits, 8);
+    std::vector<uint32_t>& cc = H.col_count;
+    parallel_for((uint64_t)nr, H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {
+        for (int64_t p = rp[a]; p < rp[b]; ++p) __atomic_fetch_add(&cc[col[p]], 1u, __ATOMIC_RELAXED);
+    });
+    return SPMM_OK;
+}
+
+// Tile the pending rows of H plus the rows [row0, row0 + nr) given by
+// (rp, col, val).  With row relabelling, rows without entries join the
+// zero-filled list and the others are taken by descending out-degree (ties
+// by row id); without it, rows keep their order.  Only whole tile rows are
+// tiled unless `last`; the remainder stays pending (copied into H).
+spmm_status_t tile_block(Handle& H, int64_t row0, int64_t nr, const int64_t* rp, const int32_t* col,
+                         const float* val, bool last, std::string& err) {
+    std::vector<RowRef> rows;
+    rows.reserve(H.pend_row.size() + (size_t)nr);
+    for (size_t i = 0; i < H.pend_row.size(); ++i)
+        rows.push_back({H.pend_row[i], H.pend_col.data() + H.pend_off[i],
+                        H.has_val ? H.pend_val.data() + H.pend_off[i] : nullptr, H.pend_off[i + 1] - H.pend_off[i]});
+    for (int64_t i = 0; i < nr; ++i) {
+        const uint64_t len = (uint64_t)(rp[i + 1] - rp[i]);
+        if (H.row_relabel && len == 0) {
+            H.zero_rows.push_back((int32_t)(row0 + i));
+            continue;
+        }
+        rows.push_back({row0 + i, col + rp[i], val ? val + rp[i] : nullptr, len});
+    }
+    if (H.row_relabel && rows.size() > 1) {
+        // counting sort by descending length, stable (pending rows precede
+        // the block's and hold smaller ids, so ties stay in row-id order);
+        // lengths >= cap share the first bucket, then are ordered exactly
+        uint64_t maxl = 0;
+        for (const RowRef& r : rows) maxl = std::max(maxl, r.len);
+        const uint64_t cap = std::min<uint64_t>(maxl, 1u << 20);
+        auto key = [cap](uint64_t len) { return cap - std::min(cap, len); };
+        std::vector<uint64_t> start(cap + 2, 0);
+        for (const RowRef& r : rows) start[key(r.len) + 1]++;
+        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+        const uint64_t nbig = start[1];
+        std::vector<RowRef> sorted(rows.size());
+        for (const RowRef& r : rows) sorted[start[key(r.len)]++] = r;
+        std::stable_sort(sorted.begin(), sorted.begin() + (int64_t)nbig,
+                         [](const RowRef& a, const RowRef& b) { return a.len > b.len; });
+        rows.swap(sorted);
+    }
+    const int64_t now = last ? (int64_t)rows.size() : (int64_t)(rows.size() / H.h * H.h);
+    spmm_status_t st = tile_rows(H, rows.data(), now, err);
+    if (st != SPMM_OK) return st;
+    // the remainder becomes the new pending set (copied before the old one
+    // it may point into is released)
+    std::vector<int64_t> prow;
+    std::vector<uint64_t> poff(1, 0);
+    std::vector<int32_t> pcol;
+    std::vector<float> pval;
+    for (size_t i = (size_t)now; i < rows.size(); ++i) {
+        prow.push_back(rows[i].row);
+        pcol.insert(pcol.end(), rows[i].col, rows[i].col + rows[i].len);
+        if (H.has_val) pval.insert(pval.end(), rows[i].val, rows[i].val + rows[i].len);
+        poff.push_back(pcol.size());
+    }
+    H.pend_row.swap(prow);
+    H.pend_off.swap(poff);
+    H.pend_col.swap(pcol);
+    H.pend_val.swap(pval);
+    return SPMM_OK;
+}
+
+}  // namespace
+
+void build_init(Handle& H, bool has_val) {
+    H.has_val = has_val;
+    H.wshift = log2_exact(H.w);
+    H.n_strips = (uint64_t)((H.n_cols + H.w - 1) / H.w);
+    if (H.n_strips == 0) H.n_strips = 1;
+    H.col_count.assign((size_t)H.n_cols, 0);
+    H.max_row_l1 = 0.0;
+    H.nnz = 0;
+    H.n_slabs = 0;
+    H.n_tiled_rows = 0;
+    H.sum_nnr = H.sum_nnc = 0;
+    H.next_row = 0;
+    H.pend_off.assign(1, 0);
+}
+
+spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* col,
+                              const float* val, bool validate, std::string& err) {
+    const int64_t n = H.n_rows;
+    if (row_ptr[0] != 0) {
+        err = "row_ptr[0] must be 0";
+        return SPMM_EINVAL;
+    }
+    if (row_ptr[n] < 0) {
+        err = "row_ptr[n_rows] is negative";
+        return SPMM_EINVAL;
+    }
+    build_init(H, val != nullptr);
+    spmm_status_t st = scan_rows(H, n, row_ptr, col, val, validate, err);
+    if (st != SPMM_OK) return st;
+    H.nnz = row_ptr[n];
+    // Column relabelling by descending in-degree (ties by column id): a
+    // counting sort over degrees, stable in the original order.
+    if (H.relabel) {
+        const std::vector<uint32_t>& indeg = H.col_count;
+        const int64_t m = H.n_cols;
+        uint32_t maxd = 0;
+        for (int64_t c = 0; c < m; ++c) maxd = std::max(maxd, indeg[c]);
+        std::vector<uint64_t> start((size_t)maxd + 2, 0);
+        for (int64_t c = 0; c < m; ++c) start[maxd - indeg[c] + 1]++;
+        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+        H.col_new.resize((size_t)m);
+        H.col_old.resize((size_t)m);
+        for (int64_t c = 0; c < m; ++c) {
+            const uint64_t r = start[maxd - indeg[c]]++;
+            H.col_new[c] = (int32_t)r;
+            H.col_old[r] = (int32_t)c;
+        }
+    }
+    try {
+        H.ent.reserve((size_t)H.nnz);
+        if (val) H.val.reserve((size_t)H.nnz);
+    } catch (const std::bad_alloc&) {
+        err = "out of host memory for the tile store";
+        return SPMM_ENOMEM;
+    }
+    // Row order (one block: the whole matrix).  With row relabelling, tile
+    // rows take the rows by descending out-degree (ties by row id), so that
+    // rows sharing the hub columns sit in the same tile rows and gather those
+    // X rows once per tile row; rows without entries are left out of the
+    // tiles and zero-filled at run time.
+    if ((st = tile_block(H, 0, n, row_ptr, col, val, true, err)) != SPMM_OK) return st;
+    return build_finish_rows(H, err);
+}
+
+spmm_status_t build_append(Handle& H, int64_t row0, int64_t nr, const int64_t* rp, const int32_t* col,
+                           const float* val, bool validate, std::string& err) {
+    if (row0 != H.next_row || nr < 0 || row0 + nr > H.n_rows) {
+        err = "rows must be appended in order: expected row " + std::to_string(H.next_row);
+        return SPMM_EINVAL;
+    }
+    if (rp[0] != 0) {
+        err = "row_ptr_local[0] must be 0";
+        return SPMM_EINVAL;
+    }
+    if ((val != nullptr) != H.has_val) {
+        err = "values must be given for every block or for none";
+        return SPMM_EINVAL;
+    }
+    spmm_status_t st = scan_rows(H, nr, rp, col, val, validate, err);
+    if (st != SPMM_OK) return st;
+    if ((st = tile_block(H, row0, nr, rp, col, val, false, err)) != SPMM_OK) return st;
+    H.nnz += rp[nr];
+    H.next_row = row0 + nr;
+    return SPMM_OK;
+}
+
+spmm_status_t build_finish_rows(Handle& H, std::string& err) {
+    if (!H.pend_row.empty()) {
+        spmm_status_t st = tile_block(H, H.next_row, 0, nullptr, nullptr, nullptr, true, err);
+        if (st != SPMM_OK) return st;
+    }
+    if (H.row_relabel) {
+        H.row_old.insert(H.row_old.end(), H.zero_rows.begin(), H.zero_rows.end());
+        std::vector<int32_t>().swap(H.zero_rows);
+        if ((int64_t)H.row_old.size() != H.n_rows) {
+            err = "internal: row order does not cover every row";
+            return SPMM_ESTATE;
+        }
+        // a relabelled handle whose rows all stayed in place needs no map
+        bool identity = H.n_tiled_rows == H.n_rows;
+        for (int64_t r = 0; r < H.n_rows && identity; ++r) identity = H.row_old[(size_t)r] == (int32_t)r;
+        if (identity) std::vector<int32_t>().swap(H.row_old);
+    }
+    std::vector<int64_t>().swap(H.pend_row);
+    std::vector<uint64_t>().swap(H.pend_off);
+    std::vector<int32_t>().swap(H.pend_col);
+    std::vector<float>().swap(H.pend_val);
     return SPMM_OK;
 }
 

@@ -237,6 +237,7 @@ spmm_status_t collect(spmm::Handle& H, int k, int dt, const spmm_tune_opts* opts
 extern "C" {
 
 spmm_status_t spmm_tile_features(spmm_handle_t h, int k, spmm_xdtype_t dt, float* feat) {
+    if (spmm_status_t rs = check_ready(h)) return rs;
     if (!h || (!feat && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
     if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
     spmm::tile_features(h->H, k, xbytes_of(dt), feat);
@@ -244,6 +245,7 @@ spmm_status_t spmm_tile_features(spmm_handle_t h, int k, spmm_xdtype_t dt, float
 }
 
 spmm_status_t spmm_get_variants(spmm_handle_t h, uint8_t* variant) {
+    if (spmm_status_t rs = check_ready(h)) return rs;
     if (!h || (!variant && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
     if (!h->H.variant.empty()) std::memcpy(variant, h->H.variant.data(), h->H.variant.size());
     return SPMM_OK;
@@ -251,7 +253,8 @@ spmm_status_t spmm_get_variants(spmm_handle_t h, uint8_t* variant) {
 
 spmm_status_t spmm_set_variants(spmm_handle_t h, const uint8_t* variant) {
     try {
-        if (!h || (!variant && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
+        if (spmm_status_t rs = check_ready(h)) return rs;
+        if (!variant && !h->H.tiles.empty()) return fail(SPMM_EINVAL, "NULL argument");
         spmm::Handle& H = h->H;
         for (size_t t = 0; t < H.tiles.size(); ++t)
             if (variant[t] >= SPMM_NUM_VARIANTS) return fail(SPMM_EINVAL, "variant out of range");
@@ -265,7 +268,8 @@ spmm_status_t spmm_set_variants(spmm_handle_t h, const uint8_t* variant) {
 spmm_status_t spmm_selector_collect(spmm_handle_t h, int k, spmm_xdtype_t dt, const spmm_tune_opts* opts,
                                     uint32_t* bucket, uint32_t* n_buckets, float* ns, hipStream_t s) {
     try {
-        if (!h || !n_buckets || !ns || (!bucket && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
+        if (spmm_status_t rs = check_ready(h)) return rs;
+        if (!n_buckets || !ns || (!bucket && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         if (h->H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "bucket timing needs device placement");
         std::vector<uint32_t> b;
@@ -285,7 +289,7 @@ spmm_status_t spmm_selector_collect(spmm_handle_t h, int k, spmm_xdtype_t dt, co
 spmm_status_t spmm_autotune(spmm_handle_t h, int k, spmm_xdtype_t dt, const spmm_tune_opts* opts,
                             uint32_t* n_buckets, float* ns, hipStream_t s) {
     try {
-        if (!h) return fail(SPMM_EINVAL, "NULL argument");
+        if (spmm_status_t rs = check_ready(h)) return rs;
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         spmm::Handle& H = h->H;
         if (H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "bucket timing needs device placement");
@@ -461,7 +465,8 @@ spmm_status_t spmm_selector_train(const float* feat, const float* target, const 
 
 spmm_status_t spmm_select_learned(spmm_handle_t h, const float* params, int k, spmm_xdtype_t dt) {
     try {
-        if (!h || !params) return fail(SPMM_EINVAL, "NULL argument");
+        if (spmm_status_t rs = check_ready(h)) return rs;
+        if (!params) return fail(SPMM_EINVAL, "NULL argument");
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         spmm::Handle& H = h->H;
         const uint64_t T = H.tiles.size();

@@ -137,6 +137,18 @@ struct Handle {
     std::vector<int32_t> row_old;      // original row of tiled row r
     int64_t n_tiled_rows = 0;
     int32_t* d_row_old = nullptr;      // device copy of row_old
+    // slab-wise build state: rows appended so far, rows not yet tiled (a
+    // partial tile row), rows without entries (zero-filled)
+    bool building = false;
+    bool validate_rows = false;
+    bool has_val_known = true;         // a slab-wise build learns it from its first block
+    int32_t fixed_variant = -1;
+    int64_t next_row = 0;
+    std::vector<int64_t> pend_row;
+    std::vector<uint64_t> pend_off;
+    std::vector<int32_t> pend_col;
+    std::vector<float> pend_val;
+    std::vector<int32_t> zero_rows;
     // encoded work
     Encoded enc;
     // device / pinned copies
@@ -180,8 +192,17 @@ inline int kc_cap(const Handle& H) {
 }
 
 // builder.cpp
+// Fields of H a build starts from (shape, tile geometry and options set).
+void build_init(Handle& H, bool has_val);
+// One-shot build of the tile store from a whole CSR (rp[0] = 0).
 spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* col,
                               const float* val, bool validate, std::string& err);
+// Slab-wise build: rows [row0, row0 + nr) with local row pointers (rp[0] =
+// 0), appended in order; columns keep the given order.
+spmm_status_t build_append(Handle& H, int64_t row0, int64_t nr, const int64_t* rp, const int32_t* col,
+                           const float* val, bool validate, std::string& err);
+// Tile the rows still pending and complete the row map.
+spmm_status_t build_finish_rows(Handle& H, std::string& err);
 spmm_status_t encode(Handle& H, std::string& err);
 // CSR of the transpose of an n_rows x n_cols CSR (rows ascending within each
 // row of the result; duplicates kept), with range checks on the input.

@@ -69,6 +69,8 @@ def _load():
         L.synth_sbm_begin.restype = ctypes.c_int
         L.synth_sbm_samples.argtypes = [i64, i64, i64, i64, ctypes.c_double, u64, vp, vp]
         L.synth_sbm_samples.restype = None
+        L.synth_set_verbose.argtypes = [ctypes.c_int]
+        L.synth_set_verbose.restype = None
         L.synth_sbm_perm.argtypes = [i64, u64, vp]
         L.synth_sbm_perm.restype = None
         _lib = L
@@ -90,6 +92,7 @@ def rmat_csr(scale: int, edge_factor: float, seed: int = SEED_GRAPH, symmetrize:
     """
     L = _load()
     nsamples = int(round(edge_factor * (1 << scale)))
+    L.synth_set_verbose(1 if progress else 0)
     h = ctypes.c_void_p()
     n = ctypes.c_int64()
     nnz = ctypes.c_int64()

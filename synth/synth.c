@@ -21,9 +21,20 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
+
+/* Progress lines on stderr while a large graph is built (0 = silent). */
+static int g_verbose = 0;
+void synth_set_verbose(int v) { g_verbose = v; }
+static void note(const char* what, int64_t done, int64_t total) {
+    if (g_verbose) {
+        fprintf(stderr, "[synth] %s: %lld / %lld\n", what, (long long)done, (long long)total);
+        fflush(stderr);
+    }
+}
 
 #define GOLDEN 0x9E3779B97F4A7C15ULL
 
@@ -164,14 +175,18 @@ static int graph_build(synth_graph* g, synth_graph** out, int64_t* n_out, int64_
     g->off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
     if (!g->cnt || !g->off) goto fail;
 
-    /* pass 1: per-row sample counts */
-    #pragma omp parallel for schedule(static, 65536)
-    for (int64_t e = 0; e < nsamples; ++e) {
-        uint32_t u, v;
-        graph_sample(g, (uint64_t)e, &u, &v);
-        if (u == v) continue;
-        __atomic_fetch_add(&g->cnt[u], 1u, __ATOMIC_RELAXED);
-        if (symmetrize) __atomic_fetch_add(&g->cnt[v], 1u, __ATOMIC_RELAXED);
+    /* pass 1: per-row sample counts (in eight chunks, for progress lines) */
+    for (int64_t c = 0; c < 8; ++c) {
+        const int64_t e0 = nsamples * c / 8, e1 = nsamples * (c + 1) / 8;
+        #pragma omp parallel for schedule(static, 65536)
+        for (int64_t e = e0; e < e1; ++e) {
+            uint32_t u, v;
+            graph_sample(g, (uint64_t)e, &u, &v);
+            if (u == v) continue;
+            __atomic_fetch_add(&g->cnt[u], 1u, __ATOMIC_RELAXED);
+            if (symmetrize) __atomic_fetch_add(&g->cnt[v], 1u, __ATOMIC_RELAXED);
+        }
+        note("samples counted", e1, nsamples);
     }
     exclusive_scan_u32_to_i64(g->cnt, g->off, n);
     g->bucket = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(g->off[n] > 0 ? g->off[n] : 1));
@@ -179,17 +194,21 @@ static int graph_build(synth_graph* g, synth_graph** out, int64_t* n_out, int64_
     memset(g->cnt, 0, sizeof(uint32_t) * (size_t)n);
 
     /* pass 2: scatter samples into their row buckets (same draws again) */
-    #pragma omp parallel for schedule(static, 65536)
-    for (int64_t e = 0; e < nsamples; ++e) {
-        uint32_t u, v;
-        graph_sample(g, (uint64_t)e, &u, &v);
-        if (u == v) continue;
-        uint32_t p = __atomic_fetch_add(&g->cnt[u], 1u, __ATOMIC_RELAXED);
-        g->bucket[g->off[u] + p] = v;
-        if (symmetrize) {
-            uint32_t q = __atomic_fetch_add(&g->cnt[v], 1u, __ATOMIC_RELAXED);
-            g->bucket[g->off[v] + q] = u;
+    for (int64_t c = 0; c < 8; ++c) {
+        const int64_t e0 = nsamples * c / 8, e1 = nsamples * (c + 1) / 8;
+        #pragma omp parallel for schedule(static, 65536)
+        for (int64_t e = e0; e < e1; ++e) {
+            uint32_t u, v;
+            graph_sample(g, (uint64_t)e, &u, &v);
+            if (u == v) continue;
+            uint32_t p = __atomic_fetch_add(&g->cnt[u], 1u, __ATOMIC_RELAXED);
+            g->bucket[g->off[u] + p] = v;
+            if (symmetrize) {
+                uint32_t q = __atomic_fetch_add(&g->cnt[v], 1u, __ATOMIC_RELAXED);
+                g->bucket[g->off[v] + q] = u;
+            }
         }
+        note("samples bucketed", e1, nsamples);
     }
 
     /* pass 3: sort each row, drop duplicates; cnt[u] becomes the unique count */
@@ -206,6 +225,7 @@ static int graph_build(synth_graph* g, synth_graph** out, int64_t* n_out, int64_
         g->cnt[u] = (uint32_t)w;
         nnz += w;
     }
+    note("rows sorted and deduplicated", n, n);
     g->nnz = nnz;
     *out = g;
     *n_out = n;
