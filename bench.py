@@ -408,12 +408,28 @@ def main() -> int:
             got = Ys[k][torch.from_numpy(sel).to(dev)].cpu().numpy()
             errs[str(k)] = oracle.frob_rel_err(got, ref)
         cpu_gflops = sum(2.0 * sel_nnz * k for k in ks) / t_cpu / 1e9
+        # second leg: the same loop with the rows spread over the host's
+        # threads (OpenMP); rows are independent, so Y is the same bits
+        t_omp = 0.0
+        threads = 1
+        for k in ks:
+            c0 = time.perf_counter()
+            ref_omp, threads = oracle.spmm_sel_omp(rp, col, None, Xh[k], sel)
+            t_omp += time.perf_counter() - c0
+            got = Ys[k][torch.from_numpy(sel).to(dev)].cpu().numpy()
+            errs[str(k)] = max(errs[str(k)], oracle.frob_rel_err(got, ref_omp))
+        omp_gflops = sum(2.0 * sel_nnz * k for k in ks) / t_omp / 1e9
+        host = host_info()
         cpu = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
                "sample": f"{sel.size} rows ({sel_nnz} nnz: rows 0-63 plus spread blocks), "
-                         f"k sweep {ks}, FP64 single-threaded CSR loop, {t_cpu:.1f}s"}
+                         f"k sweep {ks}, FP64 single-threaded CSR loop, {t_cpu:.1f}s",
+               "threaded": {"value": round(omp_gflops, 3), "unit": "GFLOP/s", "cores": threads,
+                            "kind": "oracle, OpenMP over rows", "seconds": round(t_omp, 2)},
+               **host}
         parity = {"rows": int(sel.size), "max_rel_frob_err": max(errs.values()), "per_k": errs,
                   "tolerance": 1e-6, "ok": max(errs.values()) <= 1e-6}
-        log(f"cpu oracle {cpu_gflops:.2f} GFLOP/s over {t_cpu:.1f}s; parity max err {parity['max_rel_frob_err']:.3g}")
+        log(f"cpu oracle {cpu_gflops:.2f} GFLOP/s over {t_cpu:.1f}s (1 thread), {omp_gflops:.2f} GFLOP/s "
+            f"over {t_omp:.1f}s ({threads} threads); parity max err {parity['max_rel_frob_err']:.3g}")
 
     out = {
         "metric": "SpMM GFLOP/s (2*nnz*k/s) over the k sweep, % HBM roofline; learned-tuned vs plain",
@@ -452,6 +468,25 @@ def main() -> int:
 
 
 # ---------------------------------------------------------------- other modes
+
+def host_info() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, CPU model, RAM."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["host_ram_gb"] = round(int(line.split()[1]) / 1048576, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
 
 def sample_rows(rp, n, budget_nnz):
     """Rows 0-63 (the R-MAT hubs) plus 64 evenly spread blocks of consecutive

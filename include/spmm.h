@@ -211,8 +211,25 @@ const char* spmm_last_error(void);
  *   s     : HIP stream (0 = null stream).
  * The first call on a handle copies the tile payload to HBM and allocates
  * the partial-result buffer of split tile rows (synchronous allocations).
+ *
+ * Arithmetic.  X is decoded to FP32 and multiplied by A's value in FP32.
+ * The products are summed exactly, in 64-bit fixed point: column j uses the
+ * grid 2^-f_j with f_j = 61 - e_j, where 2^e_j is the smallest power of two
+ * above (largest row L1 norm of A) * max_i |X[i][j]|, so that no partial
+ * sum can overflow.  Each FP32 product -- or the FP32 register sum of a run
+ * of one row's products inside one tile, which the ROW, HYBRID and WAVE
+ * variants form first -- is rounded once to that grid (to nearest, ties to
+ * even); Y[r][j] is the FP32 rounding of the exact sum of those grid
+ * values.  So results do not depend on the order of the sums (run to run,
+ * streamed or in HBM, any launch width) and integer X is exact.  A product
+ * smaller than 2^-(f_j+1) in magnitude, i.e. more than about 2^-62 of the
+ * column's bound, rounds to zero.  (This departs from plain FP32
+ * accumulation, which rounds every partial sum.)
+ * A NaN or an infinity anywhere in column j of X (for FP8, a NaN code)
+ * makes Y[r][j] NaN for every row r that has at least one entry; the other
+ * columns are unaffected.
  * Errors: SPMM_EINVAL (bad k/ld/pointer/dtype), SPMM_ESTATE (tiles placed in
- * host memory), SPMM_ENOMEM, SPMM_EHIP.
+ * host memory, or a slab-wise build not ended), SPMM_ENOMEM, SPMM_EHIP.
  */
 spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
                        const float* col_scale, float* Y, int64_t ldy, hipStream_t s);

@@ -41,7 +41,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
+                               "-fno-fast-math", "-fopenmp", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -61,6 +61,8 @@ def _load():
             f.restype = None
         L.oracle_spmm_sel_f32x.argtypes = [i64, vp, vp, vp, vp, vp, i64, i64, vp]
         L.oracle_spmm_sel_f32x.restype = None
+        L.oracle_spmm_sel_f32x_omp.argtypes = [i64, vp, vp, vp, vp, vp, i64, i64, vp]
+        L.oracle_spmm_sel_f32x_omp.restype = ctypes.c_int
         L.oracle_spmv_t_f64.argtypes = [i64, i64, vp, vp, vp, vp, vp]
         L.oracle_spmv_t_f64.restype = None
         for f in (L.oracle_bf16_encode, L.oracle_bf16_decode, L.oracle_e4m3_encode,
@@ -123,6 +125,21 @@ def spmm_sel(row_ptr, col, val, X, rows) -> np.ndarray:
     _load().oracle_spmm_sel_f32x(rows.shape[0], _p(rows), _p(_c(row_ptr, np.int64)),
                                  _p(_c(col, np.int32)), _p(_c(val, np.float32)), _p(X), k, k, _p(Y))
     return Y
+
+
+def spmm_sel_omp(row_ptr, col, val, X, rows):
+    """spmm_sel with the rows shared out over the host's threads (OpenMP):
+    the CPU baseline's multi-threaded leg.  Returns (Y, threads used); Y is
+    bit-identical to spmm_sel's."""
+    rows = _c(rows, np.int64)
+    k = X.shape[1]
+    Y = np.zeros((rows.shape[0], k), dtype=np.float64)
+    if rows.shape[0] == 0:
+        return Y, 1
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    used = _load().oracle_spmm_sel_f32x_omp(rows.shape[0], _p(rows), _p(_c(row_ptr, np.int64)),
+                                            _p(_c(col, np.int32)), _p(_c(val, np.float32)), _p(X), k, k, _p(Y))
+    return Y, int(used)
 
 
 def spmv_t(row_ptr, col, val, x, n_cols: int | None = None) -> np.ndarray:

@@ -5,7 +5,9 @@
  * computes.  Only the tests, the smoke check and the benchmark's CPU
  * baseline may call this code; the product library never links it, and the
  * two share no source.  Built with -O2 -ffp-contract=off so that every
- * floating-point operation is one IEEE operation in the written order.
+ * floating-point operation is one IEEE operation in the written order
+ * (and -fopenmp for the baseline's multi-threaded leg, which only spreads
+ * independent rows over threads).
  *
  * Contents
  *   - SpMM  Y = A X  in FP64, row by row (Algorithm 1: the output starts at
@@ -16,6 +18,7 @@
  *     definitions (nearest representable value, ties to even).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -57,6 +60,26 @@ void oracle_spmm_sel_f32x(int64_t nsel, const int64_t* rows, const int64_t* row_
                           int64_t ldx, double* Y) {
     for (int64_t s = 0; s < nsel; ++s)
         oracle_spmm_rows_f32x(rows[s], rows[s] + 1, row_ptr, col, val, X, k, ldx, Y + s * k, k);
+}
+
+/* The second leg of the CPU baseline: oracle_spmm_sel_f32x with the
+   selected rows shared out over the host threads (OpenMP).  Rows are
+   independent and each is summed by one thread in the written order, so the
+   result equals the single-threaded one bit for bit.  Returns the number of
+   threads used. */
+int oracle_spmm_sel_f32x_omp(int64_t nsel, const int64_t* rows, const int64_t* row_ptr,
+                             const int32_t* col, const float* val, const float* X, int64_t k,
+                             int64_t ldx, double* Y) {
+    int used = 1;
+    #pragma omp parallel
+    {
+        #pragma omp single
+        used = omp_get_num_threads();
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t s = 0; s < nsel; ++s)
+            oracle_spmm_rows_f32x(rows[s], rows[s] + 1, row_ptr, col, val, X, k, ldx, Y + s * k, k);
+    }
+    return used;
 }
 
 /* y = A^T x in FP64: every stored (r, c, v) adds v * x[r] to y[c]. */

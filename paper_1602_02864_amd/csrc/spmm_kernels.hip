@@ -130,7 +130,12 @@ struct OutScale {
 __device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
     return (unsigned long long)__double2ll_rn((double)v * scale);
 }
+// A column of X holding a NaN or an infinity has no fixed-point scale: its
+// exponent is this sentinel, its products are scaled by 0 (the sums are
+// meaningless) and every Y entry written for it is NaN.
+constexpr int32_t kNonFiniteCol = INT32_MIN;
 __device__ __forceinline__ float from_fixed(unsigned long long q, int32_t f) {
+    if (f == kNonFiniteCol) return __int_as_float(0x7FC00000);
     return (float)ldexp((double)(long long)q, -f);
 }
 
@@ -449,17 +454,23 @@ __global__ void colmax_init_kernel(uint32_t* m) {
     if (threadIdx.x < 64) m[threadIdx.x] = 0u;
 }
 
-// f_j = 61 - e with row_l1 * M_j < 2^e (0 when the bound is 0 or not finite).
+// f_j = 61 - e with row_l1 * M_j < 2^e (0 when the bound is 0);
+// kNonFiniteCol when the column holds a NaN or an infinity (M_j's bits are
+// those of |x| with the largest bit pattern, so any non-finite value wins).
 __global__ void fexp_kernel(const uint32_t* __restrict__ m, int k, double row_l1, int32_t* __restrict__ f) {
     const int j = threadIdx.x;
     if (j < 64) {
         int fj = 0;
         if (j < k) {
-            const double b = row_l1 * (double)__uint_as_float(m[j]);
-            if (b > 0.0 && b < 1.0e300) {
-                int e;
-                (void)frexp(b, &e);
-                fj = 61 - e;
+            if (m[j] >= 0x7F800000u) {
+                fj = kNonFiniteCol;
+            } else {
+                const double b = row_l1 * (double)__uint_as_float(m[j]);
+                if (b > 0.0 && b < 1.0e300) {
+                    int e;
+                    (void)frexp(b, &e);
+                    fj = 61 - e;
+                }
             }
         }
         f[j] = fj;
@@ -618,7 +629,11 @@ __global__ __launch_bounds__(256) void gather_colmax_kernel(const XT* __restrict
             for (int q = 0; q < E; ++q) {
                 float f[1];
                 XLd<XT, 1>::load(e + q, f);
-                const uint32_t bits = __float_as_uint(f[0]) & 0x7FFFFFFFu;
+                uint32_t bits = __float_as_uint(f[0]) & 0x7FFFFFFFu;
+                // the E4M3 NaN codes (S.1111.111) decode to a finite value on
+                // the fast path: mark their column as not finite here
+                if constexpr (sizeof(XT) == 1)
+                    if ((e[q] & 0x7Fu) == 0x7Fu) bits = 0x7FC00000u;
                 best[q] = bits > best[q] ? bits : best[q];
             }
         }

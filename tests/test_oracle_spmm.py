@@ -108,3 +108,18 @@ def test_frob_rel_err():
     a = np.array([[3.0, 4.0]])
     assert oracle.frob_rel_err(a, a) == 0
     assert abs(oracle.frob_rel_err(a * 1.1, a) - 0.1) < 1e-12
+
+
+def test_threaded_leg_equals_single_threaded():
+    """The CPU baseline's OpenMP leg spreads independent rows over threads:
+    its result is the single-threaded oracle's, bit for bit."""
+    rp, col = synth.rmat_csr(14, 16, seed=31)
+    n = rp.shape[0] - 1
+    val = synth.lognormal_weights(rp, col, seed=3)
+    rows = np.unique(np.concatenate([np.arange(64), np.arange(100, n, 7)]))
+    for v in (None, val):
+        X = synth.uniform(n, 5, seed=2)
+        ref = oracle.spmm_sel(rp, col, v, X, rows)
+        got, used = oracle.spmm_sel_omp(rp, col, v, X, rows)
+        assert used >= 1
+        assert np.array_equal(got, ref)
