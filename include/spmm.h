@@ -266,15 +266,46 @@ spmm_status_t spmm_quantize_x(const float* X, int64_t n, int k, int64_t ldx, spm
  *   h : built with opts.place = SPMM_PLACE_PINNED_HOST.  Other arguments as
  *       spmm_run.  compute and copy should be different streams for overlap.
  * The result is identical to spmm_run's on the same tiles (same kernels,
- * same work items).  Asynchronous, except that a call first waits on the
- * host until the previous call's kernels have finished with the ring.  The
- * first call allocates the ring.
+ * same work items).  Asynchronous: the copies into a slot wait, on the
+ * device, for the kernels that last read it -- also those of an earlier
+ * call -- so calls may be queued back to back without host
+ * synchronisation.  The first call allocates the ring.
  * Errors: SPMM_EINVAL, SPMM_ESTATE (tiles placed in HBM), SPMM_ENOMEM,
  * SPMM_EHIP.
  */
 spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
                               const float* col_scale, float* Y, int64_t ldy, hipStream_t compute,
                               hipStream_t copy);
+
+/*
+ * Y = A X with the tile payload streamed from pinned host memory (as
+ * spmm_stream_run) and Y streamed back to host memory as its tile rows
+ * finish: the device analogue of Algorithm 1's asynchronous write of output
+ * rows (Section 3.5), so that neither A nor Y has to be resident in HBM.
+ * The kernels of each transfer group write its rows of Y into a device slot
+ * (one per ring slot); a copy on `out` moves those rows -- one contiguous
+ * range per group -- to Y, and the slot is reused once that copy is done.
+ *   h   : built with place = SPMM_PLACE_PINNED_HOST and keep_row_order = 1
+ *         (or keep_order = 1), so that a group's rows are one range of Y;
+ *         SPMM_EUNSUPPORTED otherwise.
+ *   X   : device pointer as for spmm_run (resident).
+ *   Y   : pinned host memory (hipHostMalloc, or a torch tensor with
+ *         pin_memory), n_rows x k FP32, row stride ldy >= k; every element
+ *         of the n_rows x k block is written.
+ *   compute, copy, out : streams for the kernels, the host-to-device copies
+ *         and the device-to-host copies (distinct streams overlap the three).
+ * Asynchronous: Y is complete when the work queued on `out` has finished.
+ * Consecutive calls need no synchronisation (events order every reuse of a
+ * slot).  The Y slots (largest group's rows x k floats per ring slot) belong
+ * to the handle; a call with a larger k than before reallocates them after
+ * waiting for the earlier copy-outs.  Results are bit-identical to spmm_run
+ * and spmm_stream_run on a handle with the same options.
+ * Errors: as spmm_stream_run, plus SPMM_EUNSUPPORTED.
+ */
+spmm_status_t spmm_stream_run_yhost(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
+                                    const float* col_scale, float* Y, int64_t ldy, hipStream_t compute,
+                                    hipStream_t copy, hipStream_t out);
+
 
 /*
  * Semi-external SpMM with the dense matrices in host memory as well: X and
@@ -345,8 +376,11 @@ spmm_status_t spmm_pagerank(spmm_handle_t h, float damping, int iters, uint32_t 
  *             paper's H transposed), both row-major with stride r, updated in place.
  *   eps     : added to every denominator (rows of isolated vertices go to 0).
  * Gram matrices are accumulated in FP64 (deterministic order), everything
- * else in FP32.  Synchronous.  Errors: SPMM_EINVAL, SPMM_ESTATE, SPMM_ENOMEM,
- * SPMM_EHIP.
+ * else in FP32.  Asynchronous on s: the workspace (max(n, m) x r floats plus
+ * the Gram partials) belongs to hA and is kept for later calls; the first
+ * call, or one needing a larger workspace, allocates it (and waits for s
+ * before releasing a smaller one).  Errors: SPMM_EINVAL, SPMM_ESTATE,
+ * SPMM_ENOMEM, SPMM_EHIP.
  */
 spmm_status_t spmm_nmf(spmm_handle_t hA, spmm_handle_t hAT, int rank, int iters, float eps, float* W,
                        float* H, hipStream_t s);

@@ -134,6 +134,8 @@ def load_library():
     L.spmm_quantize_x.argtypes = [vp, i64, i32, i64, i32, vp, i64, vp, ctypes.c_uint32, vp]
     L.spmm_stream_run.restype = i32
     L.spmm_stream_run.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp, vp]
+    L.spmm_stream_run_yhost.restype = i32
+    L.spmm_stream_run_yhost.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp, vp, vp]
     L.spmm_pagerank.restype = i32
     L.spmm_pagerank.argtypes = [vp, ctypes.c_float, i32, ctypes.c_uint32, vp, vp, vp]
     L.spmm_nmf.restype = i32
@@ -376,6 +378,25 @@ def spmm_stream_run(h: Handle, X, Y, compute=None, copy=None, k: int | None = No
     st = L.spmm_stream_run(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
                            int(ldy), _stream(compute, X), _stream(copy))
     _check(st, "spmm_stream_run")
+
+
+def spmm_stream_run_yhost(h: Handle, X, Y, compute=None, copy=None, out=None, k: int | None = None,
+                          ldx: int | None = None, dtype: int | None = None, col_scale=None, ldy: int | None = None):
+    """Y = A X with A streamed from pinned host memory and Y streamed back to
+    pinned host memory as its tile rows finish (see spmm.h).  X: device
+    tensor; Y: pinned host float32 tensor.  Y is complete once ``out`` (the
+    device-to-host stream) has finished."""
+    _check_tensors(X, None, dtype)
+    if hasattr(Y, "data_ptr") and hasattr(Y, "dtype"):
+        if str(Y.dtype) != "torch.float32" or Y.dim() != 2 or Y.stride(1) != 1 or Y.is_cuda or not Y.is_pinned():
+            raise ValueError("Y must be a 2-D pinned host float32 tensor with unit column stride")
+    L = load_library()
+    k = X.shape[1] if k is None else k
+    ldx = X.stride(0) if ldx is None else ldx
+    ldy = Y.stride(0) if ldy is None else ldy
+    st = L.spmm_stream_run_yhost(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
+                                 int(ldy), _stream(compute, X), _stream(copy), _stream(out))
+    _check(st, "spmm_stream_run_yhost")
 
 
 SPMM_HOSTXY_BLOCKED = 1

@@ -38,6 +38,9 @@ void free_device(spmm::Handle& H) {
     if (H.d_col_old) (void)hipFree(H.d_col_old);
     if (H.d_row_old) (void)hipFree(H.d_row_old);
     H.d_row_old = nullptr;
+    if (H.d_nmf_ws) (void)hipFree(H.d_nmf_ws);
+    H.d_nmf_ws = nullptr;
+    H.nmf_ws_bytes = 0;
     if (H.d_col_count) (void)hipFree(H.d_col_count);
     H.d_col_count = nullptr;
     if (H.d_xperm) (void)hipFree(H.d_xperm);
@@ -48,6 +51,14 @@ void free_device(spmm::Handle& H) {
     for (void* q : H.ring) (void)hipFree(q);
     for (hipEvent_t e : H.ev_ready) (void)hipEventDestroy(e);
     for (hipEvent_t e : H.ev_free) (void)hipEventDestroy(e);
+    for (hipEvent_t e : H.ev_y_ready) (void)hipEventDestroy(e);
+    for (hipEvent_t e : H.ev_y_free) (void)hipEventDestroy(e);
+    H.ev_y_ready.clear();
+    H.ev_y_free.clear();
+    H.y_used.clear();
+    if (H.d_yring) (void)hipFree(H.d_yring);
+    H.d_yring = nullptr;
+    H.yslot_bytes = 0;
     for (hipEvent_t e : H.timing_ev) (void)hipEventDestroy(e);
     H.timing_ev.clear();
     H.timing_used = 0;
@@ -80,7 +91,7 @@ spmm_status_t upload(spmm::Handle& H) {
         if ((e = hipHostMalloc(&H.h_blob, nb, hipHostMallocDefault)) != hipSuccess)
             return fail(SPMM_ENOMEM, "hipHostMalloc(tile payload) failed");
         if (E.blob.size()) std::memcpy(H.h_blob, E.blob.data(), E.blob.size());
-        H.groups = spmm::make_groups(E, H.stream_bytes);
+        H.groups = spmm::make_groups(E, H.stream_bytes, H.h);
     }
     const size_t ni = E.items.size() ? E.items.size() : 1;
     if ((e = hipMalloc(&H.d_items, ni * sizeof(spmm::ItemDesc))) != hipSuccess)
@@ -320,6 +331,92 @@ void init_handle(spmm::Handle& H, int64_t n_rows, int64_t n_cols, const spmm_bui
     H.stage_bytes = o.x_stage_kib > 0 ? (uint64_t)o.x_stage_kib << 10 : 0u;
 }
 
+// Device ring of streamed mode: ring_depth slots of the largest transfer
+// group, with their ready/free events (created once per handle).
+spmm_status_t ensure_ring(spmm::Handle& H) {
+    if (!H.ring.empty()) return SPMM_OK;
+    uint64_t slot = 16;
+    for (const auto& g : H.groups) slot = std::max(slot, g.b1 - g.b0);
+    for (uint32_t r = 0; r < H.ring_depth; ++r) {
+        void* q = nullptr;
+        if (hipMalloc(&q, slot) != hipSuccess) return fail(SPMM_ENOMEM, "hipMalloc(stream ring) failed");
+        H.ring.push_back(q);
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            return fail(SPMM_EHIP, "hipEventCreate(stream ring) failed");
+        }
+        H.ev_ready.push_back(a);
+        H.ev_free.push_back(b);
+        H.ring_used.push_back(0);
+    }
+    return SPMM_OK;
+}
+
+// The HIP side of the streamed plans (stream_plan.h).  With ybase set, the
+// kernels of a group write its rows into Y slot s (rows r0..r1 of the group
+// at ybase + s * yslot floats, k per row) and copy_out moves them to the
+// host matrix yhost (row stride ldh).
+struct StreamOps {
+    spmm::Handle& H;
+    spmm::RunArgs& a;
+    hipStream_t kstream, cstream;   // compute, copy
+    hipStream_t ostream;            // output (Y to host)
+    float* yhost;
+    int64_t ldh;
+    int k;
+    spmm_status_t st;
+    bool check(hipError_t e, const char* what) {
+        if (e == hipSuccess) return true;
+        st = hip_fail(e, what);
+        return false;
+    }
+    bool wait_free(uint32_t s) { return check(hipStreamWaitEvent(cstream, H.ev_free[s], 0), "wait (slot free)"); }
+    bool copy(uint64_t g, uint32_t s) {
+        const auto& G = H.groups[g];
+        return check(hipMemcpyAsync(H.ring[s], static_cast<uint8_t*>(H.h_blob) + G.b0, G.b1 - G.b0,
+                                    hipMemcpyHostToDevice, cstream),
+                     "hipMemcpyAsync(tile group)");
+    }
+    bool record_ready(uint32_t s) { return check(hipEventRecord(H.ev_ready[s], cstream), "record (slot ready)"); }
+    bool wait_ready(uint32_t s) { return check(hipStreamWaitEvent(kstream, H.ev_ready[s], 0), "wait (slot ready)"); }
+    float* yslot(uint32_t s) const {
+        return reinterpret_cast<float*>(static_cast<uint8_t*>(H.d_yring) + (size_t)s * H.yslot_bytes);
+    }
+    bool launch(uint64_t g, uint32_t s) {
+        const auto& G = H.groups[g];
+        a.blob = static_cast<const uint8_t*>(H.ring[s]);
+        a.blob_bias = G.b0;
+        a.items = H.d_items + G.i0;
+        a.n_items = (uint32_t)(G.i1 - G.i0);
+        if (yhost) {
+            // row r of the group lands at yslot(s) + (r - r0) * k: the
+            // kernels index Y by tiled row, so hand them the slot's address
+            // moved back by r0 rows
+            a.Y = reinterpret_cast<float*>(reinterpret_cast<uintptr_t>(yslot(s)) - (uintptr_t)G.r0 * k * sizeof(float));
+            a.ldy = k;
+        }
+        return check(spmm::launch_spmm(H, a), "kernel launch");
+    }
+    bool record_free(uint32_t s) { return check(hipEventRecord(H.ev_free[s], kstream), "record (slot free)"); }
+    bool wait_y_free(uint32_t s) { return check(hipStreamWaitEvent(kstream, H.ev_y_free[s], 0), "wait (Y slot free)"); }
+    bool record_y_ready(uint32_t s) { return check(hipEventRecord(H.ev_y_ready[s], kstream), "record (Y slot ready)"); }
+    bool wait_y_ready(uint32_t s) { return check(hipStreamWaitEvent(ostream, H.ev_y_ready[s], 0), "wait (Y slot ready)"); }
+    bool copy_out(uint64_t g, uint32_t s) {
+        const auto& G = H.groups[g];
+        const size_t rows = (size_t)(G.r1 - G.r0);
+        if (!rows) return true;
+        float* dst = yhost + (size_t)G.r0 * ldh;
+        const hipError_t e = (ldh == k)
+            ? hipMemcpyAsync(dst, yslot(s), rows * k * sizeof(float), hipMemcpyDeviceToHost, ostream)
+            : hipMemcpy2DAsync(dst, (size_t)ldh * sizeof(float), yslot(s), (size_t)k * sizeof(float),
+                               (size_t)k * sizeof(float), rows, hipMemcpyDeviceToHost, ostream);
+        return check(e, "copy of finished Y rows");
+    }
+    bool record_y_free(uint32_t s) { return check(hipEventRecord(H.ev_y_free[s], ostream), "record (Y slot free)"); }
+};
+
 }  // namespace spmm_abi
 
 using namespace spmm_abi;
@@ -473,24 +570,7 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
         if (st != SPMM_OK) return st;
         if (H.n_rows == 0) return SPMM_OK;
         if ((st = prepare_device(H)) != SPMM_OK) return st;
-        if (H.ring.empty()) {
-            uint64_t slot = 16;
-            for (const auto& g : H.groups) slot = std::max(slot, g.b1 - g.b0);
-            for (uint32_t r = 0; r < H.ring_depth; ++r) {
-                void* q = nullptr;
-                if (hipMalloc(&q, slot) != hipSuccess) return fail(SPMM_ENOMEM, "hipMalloc(stream ring) failed");
-                H.ring.push_back(q);
-                hipEvent_t a = nullptr, b = nullptr;
-                if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
-                    hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
-                    if (a) (void)hipEventDestroy(a);
-                    return fail(SPMM_EHIP, "hipEventCreate(stream ring) failed");
-                }
-                H.ev_ready.push_back(a);
-                H.ev_free.push_back(b);
-                H.ring_used.push_back(0);
-            }
-        }
+        if ((st = ensure_ring(H)) != SPMM_OK) return st;
         spmm::RunArgs a{};
         if ((st = prepare_x(H, X, k, ldx, dt, compute, false, a)) != SPMM_OK) return st;
         a.dtype = dt;
@@ -505,37 +585,74 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
         // The slot/event ordering of the ring (stream_plan.h): every copy
         // into a slot waits for the kernels that last read it, also across
         // calls, so consecutive calls need no host synchronisation.
-        struct HipOps {
-            spmm::Handle& H;
-            spmm::RunArgs& a;
-            hipStream_t kstream, cstream;  // compute, copy
-            spmm_status_t st = SPMM_OK;
-            bool check(hipError_t e, const char* what) {
-                if (e == hipSuccess) return true;
-                st = hip_fail(e, what);
-                return false;
-            }
-            bool wait_free(uint32_t s) { return check(hipStreamWaitEvent(cstream, H.ev_free[s], 0), "wait (slot free)"); }
-            bool copy(uint64_t g, uint32_t s) {
-                const auto& G = H.groups[g];
-                return check(hipMemcpyAsync(H.ring[s], static_cast<uint8_t*>(H.h_blob) + G.b0, G.b1 - G.b0,
-                                            hipMemcpyHostToDevice, cstream),
-                             "hipMemcpyAsync(tile group)");
-            }
-            bool record_ready(uint32_t s) { return check(hipEventRecord(H.ev_ready[s], cstream), "record (slot ready)"); }
-            bool wait_ready(uint32_t s) { return check(hipStreamWaitEvent(kstream, H.ev_ready[s], 0), "wait (slot ready)"); }
-            bool launch(uint64_t g, uint32_t s) {
-                const auto& G = H.groups[g];
-                a.blob = static_cast<const uint8_t*>(H.ring[s]);
-                a.blob_bias = G.b0;
-                a.items = H.d_items + G.i0;
-                a.n_items = (uint32_t)(G.i1 - G.i0);
-                return check(spmm::launch_spmm(H, a), "kernel launch");
-            }
-            bool record_free(uint32_t s) { return check(hipEventRecord(H.ev_free[s], kstream), "record (slot free)"); }
-        } ops{H, a, compute, copy};
+        StreamOps ops{H, a, compute, copy, nullptr, nullptr, 0, 0, SPMM_OK};
         if (!spmm::run_stream_plan(H.groups.size(), (uint32_t)H.ring.size(), H.ring_used.data(), ops)) return ops.st;
         return zero_empty_rows(H, Y, ldy, k, compute);
+    } catch (const std::exception& ex) {
+        return fail(SPMM_EINVAL, ex.what());
+    }
+}
+
+spmm_status_t spmm_stream_run_yhost(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
+                                    const float* col_scale, float* Y, int64_t ldy, hipStream_t compute,
+                                    hipStream_t copy, hipStream_t out) {
+    try {
+        if (spmm_status_t rs = check_ready(h)) return rs;
+        spmm::Handle& H = h->H;
+        if (H.place != SPMM_PLACE_PINNED_HOST)
+            return fail(SPMM_ESTATE, "tiles are placed in HBM; build with place = SPMM_PLACE_PINNED_HOST");
+        if (!H.row_old.empty() || H.n_tiled_rows != H.n_rows)
+            return fail(SPMM_EUNSUPPORTED, "Y rows are streamed out by tile row: build with keep_row_order = 1");
+        spmm_status_t st = check_run_args(H, X, k, ldx, dt, col_scale, Y, ldy);
+        if (st != SPMM_OK) return st;
+        if (H.n_rows == 0) return SPMM_OK;
+        if ((st = prepare_device(H)) != SPMM_OK) return st;
+        if ((st = ensure_ring(H)) != SPMM_OK) return st;
+        // Y slots: the largest group's rows at this k (regrown if k grows,
+        // after the copy-outs still reading the old slots)
+        uint64_t rows_max = 1;
+        for (const auto& g : H.groups) rows_max = std::max<uint64_t>(rows_max, g.r1 - g.r0);
+        const uint64_t need = (rows_max * (uint64_t)k * sizeof(float) + 255) / 256 * 256;
+        if (need > H.yslot_bytes || H.ev_y_ready.empty()) {
+            for (size_t r = 0; r < H.y_used.size(); ++r) {
+                if (!H.y_used[r]) continue;
+                hipError_t e = hipEventSynchronize(H.ev_y_free[r]);
+                if (e != hipSuccess) return hip_fail(e, "earlier Y copy-out");
+            }
+            if (H.d_yring) (void)hipFree(H.d_yring);
+            H.d_yring = nullptr;
+            H.yslot_bytes = 0;
+            if (hipMalloc(&H.d_yring, need * H.ring.size()) != hipSuccess)
+                return fail(SPMM_ENOMEM, "hipMalloc(Y slots) failed");
+            H.yslot_bytes = need;
+            H.y_used.assign(H.ring.size(), 0);
+            while (H.ev_y_ready.size() < H.ring.size()) {
+                hipEvent_t a = nullptr, b = nullptr;
+                if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+                    hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+                    if (a) (void)hipEventDestroy(a);
+                    return fail(SPMM_EHIP, "hipEventCreate(Y slots) failed");
+                }
+                H.ev_y_ready.push_back(a);
+                H.ev_y_free.push_back(b);
+            }
+        }
+        spmm::RunArgs a{};
+        if ((st = prepare_x(H, X, k, ldx, dt, compute, false, a)) != SPMM_OK) return st;
+        a.dtype = dt;
+        a.col_scale = col_scale;
+        a.stream = compute;
+        a.combine = H.d_combine;
+        a.n_combine = (uint32_t)H.enc.combine.size();
+        a.count = H.d_count;
+        a.rmap = nullptr;
+        // the slot/event ordering of stream_plan.h, with the Y slots: a
+        // group's kernels wait for the previous copy-out of their Y slot
+        StreamOps ops{H, a, compute, copy, out, Y, ldy, k, SPMM_OK};
+        if (!spmm::run_stream_plan_yout(H.groups.size(), (uint32_t)H.ring.size(), H.ring_used.data(),
+                                        H.y_used.data(), ops))
+            return ops.st;
+        return SPMM_OK;
     } catch (const std::exception& ex) {
         return fail(SPMM_EINVAL, ex.what());
     }
@@ -745,12 +862,27 @@ spmm_status_t spmm_nmf(spmm_handle_t hA, spmm_handle_t hAT, int rank, int iters,
         spmm_status_t st = prepare_device(A);
         if (st == SPMM_OK && hAT != hA) st = prepare_device(AT);
         if (st != SPMM_OK) return st;
-        DevBufs B;
-        B.sync_on(s);
-        float* S = B.get<float>((size_t)std::max(n, m) * rank);
-        double* part = B.get<double>((size_t)spmm::gram_blocks() * rank * rank);
-        float* G = B.get<float>((size_t)rank * rank);
-        if (!S || !part || !G) return fail(SPMM_ENOMEM, "hipMalloc(NMF workspace) failed");
+        // workspace owned by hA and kept between calls, so that the call is
+        // asynchronous: S (max(n, m) x rank), the Gram partials and G
+        const size_t s_bytes = (((size_t)std::max(n, m) * rank * sizeof(float)) + 255) / 256 * 256;
+        const size_t p_bytes = ((size_t)spmm::gram_blocks() * rank * rank * sizeof(double) + 255) / 256 * 256;
+        const size_t need = s_bytes + p_bytes + (size_t)rank * rank * sizeof(float);
+        if (need > A.nmf_ws_bytes) {
+            if (A.d_nmf_ws) {
+                // the previous workspace may still be in use by queued work
+                hipError_t se = hipStreamSynchronize(s);
+                if (se != hipSuccess) return hip_fail(se, "NMF workspace resize");
+                (void)hipFree(A.d_nmf_ws);
+                A.d_nmf_ws = nullptr;
+                A.nmf_ws_bytes = 0;
+            }
+            if (hipMalloc(&A.d_nmf_ws, need) != hipSuccess) return fail(SPMM_ENOMEM, "hipMalloc(NMF workspace) failed");
+            A.nmf_ws_bytes = need;
+        }
+        uint8_t* ws = static_cast<uint8_t*>(A.d_nmf_ws);
+        float* S = reinterpret_cast<float*>(ws);
+        double* part = reinterpret_cast<double*>(ws + s_bytes);
+        float* G = reinterpret_cast<float*>(ws + s_bytes + p_bytes);
         hipError_t e;
         for (int it = 0; it < iters; ++it) {
             // H <- H * (A^T W) / (H (W^T W) + eps)
@@ -762,8 +894,6 @@ spmm_status_t spmm_nmf(spmm_handle_t hA, spmm_handle_t hAT, int rank, int iters,
             if ((st = run_device(A, Hm, rank, rank, SPMM_X_F32, nullptr, S, rank, s, false)) != SPMM_OK) return st;
             if ((e = spmm::launch_mu_update(W, S, G, n, rank, eps, s)) != hipSuccess) return hip_fail(e, "update launch");
         }
-        // the workspace is freed on return: finish the work that uses it
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "NMF execution");
         return SPMM_OK;
     } catch (const std::exception& ex) {
         return fail(SPMM_EINVAL, ex.what());

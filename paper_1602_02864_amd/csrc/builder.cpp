@@ -732,7 +732,7 @@ void encode_slab(const Handle& H, uint64_t s, ChunkOut& out, Scratch& S) {
 
 }  // namespace
 
-std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes) {
+std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes, uint32_t h) {
     // consecutive items whose payload adds up to about stream_bytes form one
     // transfer group (items are laid out back to back in the blob)
     std::vector<Handle::Group> groups;
@@ -748,7 +748,12 @@ std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes) 
         while (i1 < ni && E.items[i1].part >= 0 && E.items[i1 - 1].part >= 0 && E.items[i1].cid == E.items[i1 - 1].cid)
             ++i1;
         const uint64_t b1 = i1 < ni ? E.items[i1].blob_off : (uint64_t)E.blob.size();
-        groups.push_back({i0, i1, b0, b1});
+        // items come in tiled-row order, so the group writes one row range
+        const ItemDesc& f = E.items[i0];
+        const ItemDesc& l = E.items[i1 - 1];
+        const uint64_t r0 = (uint64_t)f.slab * h + (f.rows & 0xFFFFu);
+        const uint64_t r1 = (uint64_t)l.slab * h + (l.rows >> 16);
+        groups.push_back({i0, i1, b0, b1, r0, r1});
         i0 = i1;
     }
     return groups;

@@ -137,6 +137,8 @@ struct Handle {
     std::vector<int32_t> row_old;      // original row of tiled row r
     int64_t n_tiled_rows = 0;
     int32_t* d_row_old = nullptr;      // device copy of row_old
+    void* d_nmf_ws = nullptr;          // NMF workspace (kept between calls)
+    size_t nmf_ws_bytes = 0;
     // slab-wise build state: rows appended so far, rows not yet tiled (a
     // partial tile row), rows without entries (zero-filled)
     bool building = false;
@@ -165,6 +167,7 @@ struct Handle {
     struct Group {
         uint64_t i0, i1;          // items
         uint64_t b0, b1;          // payload bytes
+        uint64_t r0, r1;          // tiled rows the items write
     };
     std::vector<Group> groups;
     uint64_t stream_bytes = 0;
@@ -172,6 +175,11 @@ struct Handle {
     std::vector<void*> ring;      // device slots, each max group bytes
     std::vector<hipEvent_t> ev_ready, ev_free;
     std::vector<uint8_t> ring_used;  // slot has been read by a kernel (ev_free recorded)
+    // Y streamed out to host memory: one device Y slot per ring slot
+    void* d_yring = nullptr;
+    uint64_t yslot_bytes = 0;
+    std::vector<hipEvent_t> ev_y_ready, ev_y_free;
+    std::vector<uint8_t> y_used;     // slot's copy-out has been enqueued (ev_y_free recorded)
     int device = 0;
     bool uploaded = false;
     // optional timing of the SpMM launches of each run (event pairs)
@@ -211,7 +219,7 @@ spmm_status_t transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t* row_p
                             std::vector<float>& tv, std::string& err);
 // Transfer groups of streamed mode: consecutive items of about stream_bytes
 // of payload, never splitting the pieces of one split row.
-std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes);
+std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes, uint32_t h);
 spmm_status_t decode(const Handle& H, int64_t* row_ptr, int32_t* col, float* val, std::string& err);
 void tile_features(const Handle& H, int k, int xbytes, float* out);
 spmm_status_t model_tiles(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr,

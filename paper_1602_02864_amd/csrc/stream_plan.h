@@ -47,4 +47,30 @@ bool run_stream_plan(uint64_t n_groups, uint32_t R, uint8_t* used, Ops& ops) {
     return true;
 }
 
+// The same plan with Y streamed out as well (Algorithm 1's asynchronous
+// write of finished output rows): the kernels of group g write its rows of
+// Y into Y slot g mod R, and a third stream copies that slot to host memory.
+// Two more events per slot:
+//   y_ready[s]  recorded on the compute stream after the kernels that wrote
+//               Y slot s; the output stream waits for it before copying out;
+//   y_free[s]   recorded on the output stream after that copy; the compute
+//               stream waits for it before kernels write the slot again.
+// Ops also provides wait_y_free(slot) [compute], record_y_ready(slot)
+// [compute], wait_y_ready(slot) [output], copy_out(group, slot) [output] and
+// record_y_free(slot) [output]; y_used persists across calls like used.
+template <class Ops>
+bool run_stream_plan_yout(uint64_t n_groups, uint32_t R, uint8_t* used, uint8_t* y_used, Ops& ops) {
+    for (uint64_t g = 0; g < n_groups; ++g) {
+        const uint32_t slot = (uint32_t)(g % R);
+        if (used[slot] && !ops.wait_free(slot)) return false;
+        if (!ops.copy(g, slot) || !ops.record_ready(slot) || !ops.wait_ready(slot)) return false;
+        if (y_used[slot] && !ops.wait_y_free(slot)) return false;
+        if (!ops.launch(g, slot) || !ops.record_free(slot) || !ops.record_y_ready(slot)) return false;
+        if (!ops.wait_y_ready(slot) || !ops.copy_out(g, slot) || !ops.record_y_free(slot)) return false;
+        used[slot] = 1;
+        y_used[slot] = 1;
+    }
+    return true;
+}
+
 }  // namespace spmm

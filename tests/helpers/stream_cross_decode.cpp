@@ -111,7 +111,7 @@ extern "C" int64_t cross_decode(int64_t n, const int64_t* row_ptr, const int32_t
     std::string err;
     if (spmm::build_canonical(H, row_ptr, col, nullptr, true, err) != SPMM_OK) return -1;
     if (spmm::encode(H, err) != SPMM_OK) return -1;
-    const auto groups = spmm::make_groups(H.enc, stream_bytes);
+    const auto groups = spmm::make_groups(H.enc, stream_bytes, H.h);
     const int64_t ng = (int64_t)groups.size();
     if (ga < 0 || gb < 0 || ga >= ng || gb >= ng) return ng;
     uint64_t slot = 16;

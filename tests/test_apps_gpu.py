@@ -77,10 +77,35 @@ def test_nmf_matches_oracle(symmetric):
     W = torch.from_numpy(W0.copy()).cuda()
     H = torch.from_numpy(H0.copy()).cuda()
     pk.spmm_nmf(hA, hAT, W, H, iters=10, eps=1e-9)
+    torch.cuda.synchronize()
     Wr, Hr = oracle.nmf(rp, col, None, W0, H0, iters=10, eps=1e-9, AT=AT)
     assert oracle.frob_rel_err(W.cpu().numpy(), Wr) <= 1e-4
     assert oracle.frob_rel_err(H.cpu().numpy(), Hr) <= 1e-4
     assert W.min().item() >= 0 and H.min().item() >= 0
+
+
+def test_nmf_calls_are_asynchronous_and_chain():
+    """spmm_nmf returns once its work is queued (workspace kept on the
+    handle): two 5-iteration calls queued back to back, with a wider rank in
+    between that regrows the workspace, equal one 10-iteration call bit for
+    bit."""
+    import torch
+    rp, col = synth.rmat_csr(12, 8, seed=4, symmetrize=True)
+    n = rp.shape[0] - 1
+    h = pk.spmm_build_tiles(rp, col)
+    W0 = synth.uniform(n, 8, seed=synth.SEED_W)
+    H0 = synth.uniform(n, 8, seed=synth.SEED_H)
+    W1, H1 = torch.from_numpy(W0.copy()).cuda(), torch.from_numpy(H0.copy()).cuda()
+    pk.spmm_nmf(h, h, W1, H1, iters=10)
+    W2, H2 = torch.from_numpy(W0.copy()).cuda(), torch.from_numpy(H0.copy()).cuda()
+    pk.spmm_nmf(h, h, W2, H2, iters=5)
+    Wb = torch.from_numpy(synth.uniform(n, 16, seed=7)).cuda()
+    Hb = torch.from_numpy(synth.uniform(n, 16, seed=8)).cuda()
+    pk.spmm_nmf(h, h, Wb, Hb, iters=2)
+    pk.spmm_nmf(h, h, W2, H2, iters=5)
+    torch.cuda.synchronize()
+    assert torch.equal(W1, W2) and torch.equal(H1, H2)
+    h.close()
 
 
 def test_directed_apps_with_transposed_handle():

@@ -128,6 +128,58 @@ def test_host_resident_column_blocks_match_oracle(weighted):
     hs.close()
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_y_streamed_to_host(weighted):
+    """A streamed from pinned host memory and Y streamed back to pinned host
+    memory by tile-row groups: exact against the oracle for integer X on a
+    binary A, within 1e-6 otherwise, bit-identical to the in-HBM product, and
+    untouched outside the k columns of a strided Y."""
+    import torch
+    rp, col = synth.rmat_csr(15, 16, seed=11)
+    n = rp.shape[0] - 1
+    val = synth.lognormal_weights(rp, col, seed=synth.SEED_WEIGHT) if weighted else None
+    opts = dict(keep_row_order=True, item_nnz=3000)
+    hd = pk.spmm_build_tiles(rp, col, val, **opts)
+    hs = pk.spmm_build_tiles(rp, col, val, place=pk.SPMM_PLACE_PINNED_HOST, stream_kib=64, ring_depth=2, **opts)
+    comp, copy, out = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    for k in (1, 4, 33):
+        for X, exact in ((synth.int07(n, k, seed=2), not weighted), (synth.uniform(n, k, seed=3), False)):
+            Xd = torch.from_numpy(X).cuda()
+            comp.wait_stream(torch.cuda.current_stream())
+            Yh = torch.full((n, k + 2), float("nan")).pin_memory()
+            pk.spmm_stream_run_yhost(hs, Xd, Yh[:, :k], compute=comp, copy=copy, out=out)
+            Yc = torch.full((n, k), float("nan")).pin_memory()              # contiguous rows
+            pk.spmm_stream_run_yhost(hs, Xd, Yc, compute=comp, copy=copy, out=out)
+            out.synchronize()
+            Y = Yh[:, :k].numpy()
+            assert torch.isnan(Yh[:, k:]).all()
+            assert np.array_equal(Yc.numpy(), Y)
+            ref = oracle.spmm(rp, col, val, X)
+            if exact:
+                assert np.array_equal(Y.astype(np.float64), ref), k
+            else:
+                assert oracle.frob_rel_err(Y, ref) <= 1e-6, k
+            assert np.array_equal(Y, _dev_y(hd, X)), k
+    # calls queued back to back reuse the A and Y slots
+    Xd = torch.from_numpy(synth.uniform(n, 4, seed=5)).cuda()
+    ref = _dev_y(hd, synth.uniform(n, 4, seed=5))
+    comp.wait_stream(torch.cuda.current_stream())
+    outs = [torch.empty((n, 4)).pin_memory() for _ in range(3)]
+    for Yo in outs:
+        pk.spmm_stream_run_yhost(hs, Xd, Yo, compute=comp, copy=copy, out=out)
+    out.synchronize()
+    for Yo in outs:
+        assert np.array_equal(Yo.numpy(), ref)
+    hd.close()
+    hs.close()
+    # rows in degree order do not form one Y range per group
+    hr = pk.spmm_build_tiles(rp, col, val, place=pk.SPMM_PLACE_PINNED_HOST)
+    with pytest.raises(pk.SpmmError) as ei:
+        pk.spmm_stream_run_yhost(hr, Xd, torch.empty((n, 4)).pin_memory(), compute=comp, copy=copy, out=out)
+    assert ei.value.status == pk.SPMM_EUNSUPPORTED
+    hr.close()
+
+
 def test_back_to_back_streamed_calls_identical():
     """Consecutive streamed calls, enqueued without host synchronisation,
     reuse the ring slots: each call's first copies must wait for the previous

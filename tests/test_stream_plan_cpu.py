@@ -9,6 +9,8 @@
   for a slot only from the R-th group of a call on (the ordering the ring
   had before the "slot used" state was kept across calls) must fail the
   same check as soon as two calls follow each other.
+* The same with Y streamed out to host memory (a third stream copies each
+  group's finished rows out of a device Y slot).
 * What a kernel would gather from a slot overwritten too early: the
   library's builder, compiled with g++ (tests/helpers/stream_cross_decode.cpp),
   decodes one transfer group's work items against another group's payload;
@@ -36,7 +38,8 @@ def plan_lib(tmp_path_factory):
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I", CSRC,
                            os.path.join(HELP, "stream_plan_check.cpp"), "-o", out])
     L = ctypes.CDLL(out)
-    for f in (L.stream_plan_violations, L.legacy_plan_violations):
+    for f in (L.stream_plan_violations, L.legacy_plan_violations, L.yout_plan_violations,
+              L.yout_nowait_plan_violations):
         f.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
         f.restype = ctypes.c_int
     return L
@@ -60,6 +63,19 @@ def decode_lib(tmp_path_factory):
 def test_ring_plan_orders_every_copy_after_its_readers(plan_lib, groups, ring):
     for calls in (1, 2, 4):
         assert plan_lib.stream_plan_violations(groups, ring, calls) == 0, calls
+
+
+@pytest.mark.parametrize("groups,ring", [(1, 2), (2, 2), (5, 2), (7, 3), (16, 4), (40, 16), (3, 16)])
+def test_y_out_plan_orders_kernels_and_copy_outs(plan_lib, groups, ring):
+    """Y streamed out through per-slot device buffers: kernels writing a Y
+    slot follow the earlier copy-outs of that slot, and each copy-out
+    follows its group's kernels -- within a call and across calls.  Without
+    the wait for the previous copy-out the check fails."""
+    for calls in (1, 2, 4):
+        assert plan_lib.yout_plan_violations(groups, ring, calls) == 0, calls
+    if groups > ring:
+        assert plan_lib.yout_nowait_plan_violations(groups, ring, 1) > 0
+    assert plan_lib.yout_nowait_plan_violations(groups, ring, 2) > 0
 
 
 @pytest.mark.parametrize("groups,ring", [(1, 2), (2, 2), (5, 2), (7, 3), (40, 16)])
