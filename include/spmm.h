@@ -127,7 +127,17 @@ typedef struct {
                                  rows without entries are zero-filled.  1 (or
                                  keep_order = 1): tile rows take the given row
                                  order                                           */
+    uint32_t format;         /* SPMM_FORMAT_TILES (0, default): the tile store.
+                                 SPMM_FORMAT_CSR: the untiled baseline (V-csr) --
+                                 rows by descending length, columns in in-degree
+                                 order, one lane group, wavefront or several
+                                 wavefronts per row by length, FP32 register sums;
+                                 binary A, FP32 X, HBM only (spmm_run and the
+                                 paths built on it: PageRank, NMF, eigensolver)  */
 } spmm_build_opts;
+
+#define SPMM_FORMAT_TILES 0u
+#define SPMM_FORMAT_CSR 1u
 
 typedef struct spmm_handle_s* spmm_handle_t;
 

@@ -30,6 +30,7 @@ SPMM_NUM_FEATURES = 8
 VARIANT_NAMES = ("coo", "row", "hybrid", "wave")
 # spmm_place_t
 SPMM_PLACE_DEVICE, SPMM_PLACE_PINNED_HOST = 0, 1
+SPMM_FORMAT_TILES, SPMM_FORMAT_CSR = 0, 1
 
 SPMM_MAX_BUCKETS = 128
 # cost-model parameter layout (one float array; weights row-major [in][out])
@@ -62,7 +63,8 @@ class spmm_build_opts(ctypes.Structure):
                 ("validate", ctypes.c_uint32), ("max_kc", ctypes.c_uint32),
                 ("keep_order", ctypes.c_uint32), ("stream_kib", ctypes.c_uint32),
                 ("ring_depth", ctypes.c_uint32), ("x_stage_kib", ctypes.c_int32),
-                ("transpose", ctypes.c_uint32), ("keep_row_order", ctypes.c_uint32)]
+                ("transpose", ctypes.c_uint32), ("keep_row_order", ctypes.c_uint32),
+                ("format", ctypes.c_uint32)]
 
 
 class spmm_stats_t(ctypes.Structure):
@@ -248,7 +250,7 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
                      item_nnz: int = 0, place: int = SPMM_PLACE_DEVICE, threads: int = 0,
                      validate: bool = True, max_kc: int = 0, keep_order: bool = False,
                      stream_kib: int = 0, ring_depth: int = 0, x_stage_kib: int = 0,
-                     transpose: bool = False, keep_row_order: bool = False) -> Handle:
+                     transpose: bool = False, keep_row_order: bool = False, format: int = 0) -> Handle:
     L = load_library()
     rp = _host(row_ptr, np.int64)
     ci = _host(col_idx, np.int32)
@@ -257,7 +259,7 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
     n_cols = n_rows if n_cols is None else int(n_cols)
     o = spmm_build_opts(tile_rows, tile_cols, fixed_variant, item_nnz, place, threads,
                         int(bool(validate)), max_kc, int(bool(keep_order)), stream_kib, ring_depth,
-                        int(x_stage_kib), int(bool(transpose)), int(bool(keep_row_order)))
+                        int(x_stage_kib), int(bool(transpose)), int(bool(keep_row_order)), int(format))
     out = ctypes.c_void_p()
     st = L.spmm_build_tiles(n_rows, n_cols, rp.ctypes.data, None if ci is None or ci.size == 0 else ci.ctypes.data,
                             None if va is None else va.ctypes.data, ctypes.byref(o), ctypes.byref(out))
@@ -267,10 +269,10 @@ def spmm_build_tiles(row_ptr, col_idx, values=None, n_cols: int | None = None, *
 
 def _opts(tile_rows=0, tile_cols=0, fixed_variant=-1, item_nnz=0, place=SPMM_PLACE_DEVICE, threads=0,
           validate=True, max_kc=0, keep_order=False, stream_kib=0, ring_depth=0, x_stage_kib=0,
-          transpose=False, keep_row_order=False):
+          transpose=False, keep_row_order=False, format=0):
     return spmm_build_opts(tile_rows, tile_cols, fixed_variant, item_nnz, place, threads, int(bool(validate)),
                            max_kc, int(bool(keep_order)), stream_kib, ring_depth, int(x_stage_kib),
-                           int(bool(transpose)), int(bool(keep_row_order)))
+                           int(bool(transpose)), int(bool(keep_row_order)), int(format))
 
 
 def spmm_build_begin(n_rows: int, n_cols: int | None = None, **opts) -> Handle:

@@ -38,6 +38,15 @@ void free_device(spmm::Handle& H) {
     if (H.d_col_old) (void)hipFree(H.d_col_old);
     if (H.d_row_old) (void)hipFree(H.d_row_old);
     H.d_row_old = nullptr;
+    {
+        spmm::CsrStore& C = H.csr;
+        for (void* q : {(void*)C.d_rp, (void*)C.d_col, (void*)C.d_seg, (void*)C.d_srow, (void*)C.d_pb, (void*)C.d_part})
+            if (q) (void)hipFree(q);
+        C.d_rp = nullptr;
+        C.d_col = nullptr;
+        C.d_seg = C.d_srow = C.d_pb = nullptr;
+        C.d_part = nullptr;
+    }
     if (H.d_nmf_ws) (void)hipFree(H.d_nmf_ws);
     H.d_nmf_ws = nullptr;
     H.nmf_ws_bytes = 0;
@@ -118,6 +127,26 @@ spmm_status_t upload(spmm::Handle& H) {
         if ((e = hipMemcpy(H.d_col_old, H.col_old.data(), sizeof(int32_t) * (size_t)H.n_cols,
                            hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "hipMemcpy(column order)");
+    }
+    if (H.format == SPMM_FORMAT_CSR) {
+        spmm::CsrStore& C = H.csr;
+        auto put = [&](auto** dst, const auto& v, const char* what) -> spmm_status_t {
+            const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(v[0]);
+            if (hipMalloc(reinterpret_cast<void**>(dst), bytes) != hipSuccess)
+                return fail(SPMM_ENOMEM, std::string("hipMalloc(") + what + ") failed");
+            if (!v.empty()) {
+                hipError_t ce = hipMemcpy(*dst, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice);
+                if (ce != hipSuccess) return hip_fail(ce, what);
+            }
+            return SPMM_OK;
+        };
+        spmm_status_t ps;
+        if ((ps = put(&C.d_rp, C.rp, "CSR row pointers")) != SPMM_OK || (ps = put(&C.d_col, C.col, "CSR columns")) != SPMM_OK ||
+            (ps = put(&C.d_seg, C.seg, "CSR segments")) != SPMM_OK || (ps = put(&C.d_srow, C.srow, "CSR split rows")) != SPMM_OK ||
+            (ps = put(&C.d_pb, C.pb, "CSR pieces")) != SPMM_OK)
+            return ps;
+        if (hipMalloc(&C.d_part, std::max<int64_t>(C.n_pieces, 1) * 32 * sizeof(float)) != hipSuccess)
+            return fail(SPMM_ENOMEM, "hipMalloc(CSR partial sums) failed");
     }
     if (!H.row_old.empty()) {
         if ((e = hipMalloc(&H.d_row_old, sizeof(int32_t) * H.row_old.size())) != hipSuccess)
@@ -232,6 +261,8 @@ spmm_status_t zero_empty_rows(const spmm::Handle& H, float* Y, int64_t ldy, int 
 
 spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt, const float* col_scale,
                          float* Y, int64_t ldy, hipStream_t s, bool x_in_handle_order) {
+    if (H.format == SPMM_FORMAT_CSR && dt != SPMM_X_F32)
+        return fail(SPMM_EUNSUPPORTED, "the CSR format takes FP32 X");
     spmm::RunArgs a{};
     spmm_status_t st = prepare_x(H, X, k, ldx, dt, s, x_in_handle_order, a);
     if (st != SPMM_OK) return st;
@@ -247,6 +278,7 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
     a.combine = H.d_combine;
     a.n_combine = (uint32_t)H.enc.combine.size();
     a.count = H.d_count;
+    a.part = H.d_part;
     a.rmap = H.d_row_old;
     hipEvent_t* ev = nullptr;
     if (H.timing) {
@@ -262,7 +294,9 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
         hipError_t re = hipEventRecord(ev[0], s);
         if (re != hipSuccess) return hip_fail(re, "hipEventRecord");
     }
-    hipError_t e = spmm::launch_spmm(H, a);
+    hipError_t e = H.format == SPMM_FORMAT_CSR
+        ? spmm::launch_csr(H, static_cast<const float*>(a.X), a.ldx, k, Y, ldy, s)
+        : spmm::launch_spmm(H, a);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return zero_empty_rows(H, Y, ldy, k, s);
@@ -290,6 +324,7 @@ spmm_status_t launch_items_only(spmm::Handle& H, const void* X, int k, int64_t l
     a.combine = H.d_combine;
     a.n_combine = (uint32_t)H.enc.combine.size();
     a.count = H.d_count;
+    a.part = H.d_part;
     a.rmap = H.d_row_old;
     hipError_t e = spmm::launch_spmm(H, a);
     return e == hipSuccess ? SPMM_OK : hip_fail(e, "kernel launch");
@@ -310,6 +345,9 @@ spmm_status_t parse_opts(const spmm_build_opts* opts, spmm_build_opts& o) {
     if (o.fixed_variant >= SPMM_NUM_VARIANTS) return fail(SPMM_EINVAL, "unknown variant");
     if (o.place != SPMM_PLACE_DEVICE && o.place != SPMM_PLACE_PINNED_HOST) return fail(SPMM_EINVAL, "unknown placement");
     if (o.transpose > 1) return fail(SPMM_EINVAL, "transpose must be 0 or 1");
+    if (o.format != SPMM_FORMAT_TILES && o.format != SPMM_FORMAT_CSR) return fail(SPMM_EINVAL, "unknown format");
+    if (o.format == SPMM_FORMAT_CSR && o.place != SPMM_PLACE_DEVICE)
+        return fail(SPMM_EUNSUPPORTED, "the CSR format runs in HBM only");
     const uint32_t ring = o.ring_depth ? o.ring_depth : 3u;
     if (ring < 2 || ring > 16) return fail(SPMM_EINVAL, "ring_depth must be in 2..16");
     return SPMM_OK;
@@ -318,6 +356,7 @@ spmm_status_t parse_opts(const spmm_build_opts* opts, spmm_build_opts& o) {
 void init_handle(spmm::Handle& H, int64_t n_rows, int64_t n_cols, const spmm_build_opts& o) {
     H.n_rows = n_rows;
     H.n_cols = n_cols;
+    H.format = o.format;
     H.h = o.tile_rows;
     H.w = o.tile_cols;
     H.item_nnz = o.item_nnz;
@@ -455,6 +494,13 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
         spmm::Handle& H = hs->H;
         init_handle(H, n_rows, n_cols, o);
         std::string err;
+        if (o.format == SPMM_FORMAT_CSR) {
+            if (values) return fail(SPMM_EUNSUPPORTED, "the CSR format takes a binary matrix (values = NULL)");
+            st = spmm::build_csr(H, row_ptr, col_idx, o.validate != 0, err);
+            if (st != SPMM_OK) return fail(st, err);
+            *out = hs.release();
+            return SPMM_OK;
+        }
         st = spmm::build_canonical(H, row_ptr, col_idx, values, o.validate != 0, err);
         if (st != SPMM_OK) return fail(st, err);
         if (o.fixed_variant >= 0) std::fill(H.variant.begin(), H.variant.end(), (uint8_t)o.fixed_variant);
@@ -478,6 +524,7 @@ spmm_status_t spmm_build_begin(int64_t n_rows, int64_t n_cols, const spmm_build_
         spmm_status_t st = parse_opts(opts, o);
         if (st != SPMM_OK) return st;
         if (o.transpose) return fail(SPMM_EUNSUPPORTED, "a slab-wise build cannot transpose; build A^T's rows instead");
+        if (o.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "a slab-wise build makes the tile store");
         std::unique_ptr<spmm_handle_s> hs(new spmm_handle_s);
         spmm::Handle& H = hs->H;
         init_handle(H, n_rows, n_cols, o);
@@ -581,6 +628,7 @@ spmm_status_t spmm_stream_run(spmm_handle_t h, const void* X, int k, int64_t ldx
         a.combine = H.d_combine;
         a.n_combine = (uint32_t)H.enc.combine.size();
         a.count = H.d_count;
+        a.part = H.d_part;
         a.rmap = H.d_row_old;
         // The slot/event ordering of the ring (stream_plan.h): every copy
         // into a slot waits for the kernels that last read it, also across
@@ -645,6 +693,7 @@ spmm_status_t spmm_stream_run_yhost(spmm_handle_t h, const void* X, int k, int64
         a.combine = H.d_combine;
         a.n_combine = (uint32_t)H.enc.combine.size();
         a.count = H.d_count;
+        a.part = H.d_part;
         a.rmap = nullptr;
         // the slot/event ordering of stream_plan.h, with the Y slots: a
         // group's kernels wait for the previous copy-out of their Y slot

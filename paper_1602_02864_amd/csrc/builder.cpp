@@ -390,6 +390,25 @@ spmm_status_t tile_block(Handle& H, int64_t row0, int64_t nr, const int64_t* rp,
 
 }  // namespace
 
+// Column relabelling by descending in-degree (ties by column id) from the
+// column counts: a counting sort over degrees, stable in the original order.
+static void relabel_columns(Handle& H) {
+    const std::vector<uint32_t>& indeg = H.col_count;
+    const int64_t m = H.n_cols;
+    uint32_t maxd = 0;
+    for (int64_t c = 0; c < m; ++c) maxd = std::max(maxd, indeg[c]);
+    std::vector<uint64_t> start((size_t)maxd + 2, 0);
+    for (int64_t c = 0; c < m; ++c) start[maxd - indeg[c] + 1]++;
+    for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+    H.col_new.resize((size_t)m);
+    H.col_old.resize((size_t)m);
+    for (int64_t c = 0; c < m; ++c) {
+        const uint64_t r = start[maxd - indeg[c]]++;
+        H.col_new[c] = (int32_t)r;
+        H.col_old[r] = (int32_t)c;
+    }
+}
+
 void build_init(Handle& H, bool has_val) {
     H.has_val = has_val;
     H.wshift = log2_exact(H.w);
@@ -420,24 +439,8 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
     spmm_status_t st = scan_rows(H, n, row_ptr, col, val, validate, err);
     if (st != SPMM_OK) return st;
     H.nnz = row_ptr[n];
-    // Column relabelling by descending in-degree (ties by column id): a
-    // counting sort over degrees, stable in the original order.
-    if (H.relabel) {
-        const std::vector<uint32_t>& indeg = H.col_count;
-        const int64_t m = H.n_cols;
-        uint32_t maxd = 0;
-        for (int64_t c = 0; c < m; ++c) maxd = std::max(maxd, indeg[c]);
-        std::vector<uint64_t> start((size_t)maxd + 2, 0);
-        for (int64_t c = 0; c < m; ++c) start[maxd - indeg[c] + 1]++;
-        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
-        H.col_new.resize((size_t)m);
-        H.col_old.resize((size_t)m);
-        for (int64_t c = 0; c < m; ++c) {
-            const uint64_t r = start[maxd - indeg[c]]++;
-            H.col_new[c] = (int32_t)r;
-            H.col_old[r] = (int32_t)c;
-        }
-    }
+    // Column relabelling by descending in-degree (ties by column id).
+    if (H.relabel) relabel_columns(H);
     try {
         H.ent.reserve((size_t)H.nnz);
         if (val) H.val.reserve((size_t)H.nnz);
@@ -452,6 +455,74 @@ spmm_status_t build_canonical(Handle& H, const int64_t* row_ptr, const int32_t* 
     // tiles and zero-filled at run time.
     if ((st = tile_block(H, 0, n, row_ptr, col, val, true, err)) != SPMM_OK) return st;
     return build_finish_rows(H, err);
+}
+
+spmm_status_t build_csr(Handle& H, const int64_t* row_ptr, const int32_t* col, bool validate, std::string& err) {
+    const int64_t n = H.n_rows;
+    if (row_ptr[0] != 0 || row_ptr[n] < 0) {
+        err = "row_ptr[0] must be 0 and row_ptr[n_rows] >= 0";
+        return SPMM_EINVAL;
+    }
+    build_init(H, false);
+    spmm_status_t st = scan_rows(H, n, row_ptr, col, nullptr, validate, err);
+    if (st != SPMM_OK) return st;
+    H.nnz = row_ptr[n];
+    if (H.relabel) relabel_columns(H);
+    CsrStore& C = H.csr;
+    // rows by descending length, ties by row id (stable counting sort on
+    // cap - min(length, cap), then the longest rows ordered exactly)
+    uint64_t maxl = 0;
+    for (int64_t r = 0; r < n; ++r) maxl = std::max<uint64_t>(maxl, (uint64_t)(row_ptr[r + 1] - row_ptr[r]));
+    const uint64_t cap = std::min<uint64_t>(maxl, 1u << 20);
+    auto key = [&](int64_t r) { return cap - std::min<uint64_t>(cap, (uint64_t)(row_ptr[r + 1] - row_ptr[r])); };
+    std::vector<uint64_t> start(cap + 2, 0);
+    for (int64_t r = 0; r < n; ++r) start[key(r) + 1]++;
+    for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+    const uint64_t nbig = start[1];
+    H.row_old.resize((size_t)n);
+    for (int64_t r = 0; r < n; ++r) H.row_old[start[key(r)]++] = (int32_t)r;
+    std::stable_sort(H.row_old.begin(), H.row_old.begin() + (int64_t)nbig, [&](int32_t a, int32_t b) {
+        return row_ptr[a + 1] - row_ptr[a] > row_ptr[b + 1] - row_ptr[b];
+    });
+    C.rp.resize((size_t)n + 1);
+    C.rp[0] = 0;
+    for (int64_t r = 0; r < n; ++r) C.rp[r + 1] = C.rp[r] + (row_ptr[H.row_old[r] + 1] - row_ptr[H.row_old[r]]);
+    C.col.resize((size_t)H.nnz);
+    const int32_t* cmap = H.relabel ? H.col_new.data() : nullptr;
+    parallel_for((uint64_t)n, H.threads, 1 << 12, [&](uint64_t a, uint64_t b) {
+        for (uint64_t r = a; r < b; ++r) {
+            const int64_t o = H.row_old[r];
+            int32_t* dst = C.col.data() + C.rp[r];
+            const int64_t len = row_ptr[o + 1] - row_ptr[o];
+            for (int64_t p = 0; p < len; ++p) {
+                const int32_t c = col[row_ptr[o] + p];
+                dst[p] = cmap ? cmap[c] : c;
+            }
+            if (cmap) std::sort(dst, dst + len);
+        }
+    });
+    // row classes: split rows first, then wavefront rows, then group rows
+    C.seg.clear();
+    C.srow.clear();
+    C.pb.assign(1, 0);
+    C.n_split = C.n_wave_rows = C.n_pieces = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t len = C.rp[r + 1] - C.rp[r];
+        if (len <= kCsrWaveMin) break;
+        C.n_wave_rows = r + 1;
+        if (len > kCsrPiece) {
+            C.srow.push_back(r);
+            for (int64_t q = C.rp[r]; q < C.rp[r + 1]; q += kCsrPiece)
+                C.seg.insert(C.seg.end(), {r, q, std::min(C.rp[r + 1], q + kCsrPiece), C.n_pieces++});
+            C.pb.push_back(C.n_pieces);
+            C.n_split++;
+        } else {
+            C.seg.insert(C.seg.end(), {r, C.rp[r], C.rp[r + 1], -1});
+        }
+    }
+    C.n_seg = (int64_t)C.seg.size() / 4;
+    H.n_tiled_rows = n;   // every row is written by the kernels (empty ones with zeros)
+    return SPMM_OK;
 }
 
 spmm_status_t build_append(Handle& H, int64_t row0, int64_t nr, const int64_t* rp, const int32_t* col,
@@ -891,6 +962,25 @@ namespace spmm {
 // entries; sort them back into CSR order.
 spmm_status_t decode(const Handle& H, int64_t* row_ptr, int32_t* col, float* val,
                      std::string& err) {
+    if (H.format == SPMM_FORMAT_CSR) {
+        // the CSR store in the original row and column order
+        const CsrStore& C = H.csr;
+        std::vector<int64_t> len((size_t)H.n_rows, 0), at((size_t)H.n_rows, 0);
+        for (int64_t r = 0; r < H.n_rows; ++r) len[(size_t)H.row_old[r]] = C.rp[r + 1] - C.rp[r];
+        row_ptr[0] = 0;
+        for (int64_t r = 0; r < H.n_rows; ++r) row_ptr[r + 1] = row_ptr[r] + len[(size_t)r];
+        for (int64_t r = 0; r < H.n_rows; ++r) {
+            const int64_t o = H.row_old[r];
+            int32_t* dst = col + row_ptr[o];
+            for (int64_t p = C.rp[r]; p < C.rp[r + 1]; ++p)
+                *dst++ = H.relabel ? H.col_old[(size_t)C.col[(size_t)p]] : C.col[(size_t)p];
+            std::sort(col + row_ptr[o], dst);
+            if (val) std::fill(val + row_ptr[o], val + row_ptr[o + 1], 1.0f);
+        }
+        (void)at;
+        (void)err;
+        return SPMM_OK;
+    }
     static const uint8_t empty_payload[16] = {};
     const uint8_t* blob = H.enc.blob.empty() ? static_cast<const uint8_t*>(H.h_blob) : H.enc.blob.data();
     if (!blob && H.blob_bytes == 0) blob = empty_payload;

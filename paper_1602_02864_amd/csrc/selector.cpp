@@ -269,6 +269,7 @@ spmm_status_t spmm_selector_collect(spmm_handle_t h, int k, spmm_xdtype_t dt, co
                                     uint32_t* bucket, uint32_t* n_buckets, float* ns, hipStream_t s) {
     try {
         if (spmm_status_t rs = check_ready(h)) return rs;
+        if (h->H.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "variants are chosen per tile");
         if (!n_buckets || !ns || (!bucket && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         if (h->H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "bucket timing needs device placement");
@@ -290,6 +291,7 @@ spmm_status_t spmm_autotune(spmm_handle_t h, int k, spmm_xdtype_t dt, const spmm
                             uint32_t* n_buckets, float* ns, hipStream_t s) {
     try {
         if (spmm_status_t rs = check_ready(h)) return rs;
+        if (h->H.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "variants are chosen per tile");
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         spmm::Handle& H = h->H;
         if (H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "bucket timing needs device placement");
@@ -466,6 +468,7 @@ spmm_status_t spmm_selector_train(const float* feat, const float* target, const 
 spmm_status_t spmm_select_learned(spmm_handle_t h, const float* params, int k, spmm_xdtype_t dt) {
     try {
         if (spmm_status_t rs = check_ready(h)) return rs;
+        if (h->H.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "variants are chosen per tile");
         if (!params) return fail(SPMM_EINVAL, "NULL argument");
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         spmm::Handle& H = h->H;

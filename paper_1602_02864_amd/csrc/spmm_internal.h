@@ -100,8 +100,29 @@ struct Encoded {
     uint64_t variant_nnz[SPMM_NUM_VARIANTS] = {};
 };
 
+// Untiled CSR store (format SPMM_FORMAT_CSR, the V-csr baseline): rows in
+// order of descending length (row_old maps them back), columns in the
+// handle's column order, sorted within each row.
+constexpr int64_t kCsrWaveMin = 128;  // rows longer than this: one wavefront each
+constexpr int64_t kCsrPiece = 8192;   // rows longer than this: pieces of this many entries
+struct CsrStore {
+    std::vector<int64_t> rp;          // n_rows + 1, in row order
+    std::vector<int32_t> col;
+    std::vector<int64_t> seg;         // per wavefront segment: row, first entry, end entry, partial slot or -1
+    std::vector<int64_t> srow, pb;    // split rows; their first partial slot (n_split + 1 entries)
+    int64_t n_seg = 0, n_split = 0, n_wave_rows = 0, n_pieces = 0;
+    int64_t* d_rp = nullptr;
+    int32_t* d_col = nullptr;
+    int64_t* d_seg = nullptr;
+    int64_t* d_srow = nullptr;
+    int64_t* d_pb = nullptr;
+    float* d_part = nullptr;          // n_pieces x 32 partial sums
+};
+
 struct Handle {
     int64_t n_rows = 0, n_cols = 0, nnz = 0;
+    uint32_t format = SPMM_FORMAT_TILES;
+    CsrStore csr;
     uint32_t h = 0, w = 0, wshift = 0;
     uint32_t item_nnz = 0;
     uint32_t threads = 0;
@@ -211,6 +232,8 @@ spmm_status_t build_append(Handle& H, int64_t row0, int64_t nr, const int64_t* r
                            const float* val, bool validate, std::string& err);
 // Tile the rows still pending and complete the row map.
 spmm_status_t build_finish_rows(Handle& H, std::string& err);
+// The untiled CSR store of a binary matrix (format SPMM_FORMAT_CSR).
+spmm_status_t build_csr(Handle& H, const int64_t* row_ptr, const int32_t* col, bool validate, std::string& err);
 spmm_status_t encode(Handle& H, std::string& err);
 // CSR of the transpose of an n_rows x n_cols CSR (rows ascending within each
 // row of the result; duplicates kept), with range checks on the input.
@@ -244,11 +267,15 @@ struct RunArgs {
     uint32_t n_items;
     const CombineDesc* combine;  // device
     uint32_t n_combine;
+    int64_t* part;               // device, split-row partial sums (n_parts * column chunk)
     uint32_t* count;             // device, n_combine counters, zero between launches
     const int32_t* fexp;         // device, per column of X: fixed-point exponent
     const int32_t* rmap;         // device, original row of each tiled row (NULL: identity)
 };
 hipError_t launch_spmm(const Handle& H, const RunArgs& a);
+// csr_kernels.hip: Y = A X over the CSR store, FP32 X in the handle's
+// column order (k columns, row stride ldx), Y rows through H.d_row_old.
+hipError_t launch_csr(const Handle& H, const float* X, int64_t ldx, int k, float* Y, int64_t ldy, hipStream_t s);
 // Zero the k columns of the Y rows that have no entries (the original rows
 // rmap[n_tiled .. n_rows) of a row-relabelled handle).
 hipError_t launch_zero_rows(float* Y, int64_t ldy, int k, const int32_t* rows, int64_t count, hipStream_t s);

@@ -528,13 +528,13 @@ hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, true>), dim3(grid), dim3(64 * kWaves), bytes,
                                        a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
-                                       H.d_part, a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift, (uint32_t)ns);
+                                       a.part, a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift, (uint32_t)ns);
                 } else {
                     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&spmm_items_staged<KC, VW, XT, false>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     hipLaunchKernelGGL((spmm_items_staged<KC, VW, XT, false>), dim3(grid), dim3(64 * kWaves), bytes,
                                        a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy,
-                                       H.d_part, a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift, (uint32_t)ns);
+                                       a.part, a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift, (uint32_t)ns);
                 }
                 return hipGetLastError();
             }
@@ -546,11 +546,11 @@ hipError_t launch_one(const Handle& H, const RunArgs& a, const XT* X, float* Y,
     const uint32_t grid = (a.n_items + wpb - 1) / wpb;
     if (H.has_val)
         hipLaunchKernelGGL((spmm_items<KC, VW, XT, true>), dim3(grid), dim3(64 * wpb), (size_t)per_wave * wpb,
-                           a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part,
+                           a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, a.part,
                            a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift);
     else
         hipLaunchKernelGGL((spmm_items<KC, VW, XT, false>), dim3(grid), dim3(64 * wpb), (size_t)per_wave * wpb,
-                           a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, H.d_part,
+                           a.stream, a.items, a.n_items, a.blob, a.blob_bias, X, a.ldx, Y, a.ldy, a.part,
                            a.combine, a.count, yscale, fexp, a.rmap, H.h, H.wshift);
     return hipGetLastError();
 }

@@ -233,3 +233,22 @@ def test_row_order_by_degree_and_empty_rows_untiled():
         drp, dcol = pk.spmm_decode_tiles(hd, col.shape[0])
         assert np.array_equal(drp, rp) and np.array_equal(dcol, col), opts
         hd.close()
+
+
+def test_csr_format_round_trip_and_limits():
+    """The untiled CSR store (V-csr baseline) decodes to the input; it takes
+    binary matrices in HBM only."""
+    rp, col = synth.rmat_csr(13, 16, seed=12)
+    for keep in (False, True):
+        h = pk.spmm_build_tiles(rp, col, format=pk.SPMM_FORMAT_CSR, keep_order=keep)
+        drp, dcol = pk.spmm_decode_tiles(h, col.shape[0])
+        assert np.array_equal(drp, rp) and np.array_equal(dcol, col)
+        assert pk.spmm_get_stats(h)["nnz"] == col.shape[0]
+        h.close()
+    val = np.ones(col.shape[0], np.float32)
+    with pytest.raises(pk.SpmmError) as ei:
+        pk.spmm_build_tiles(rp, col, val, format=pk.SPMM_FORMAT_CSR)
+    assert ei.value.status == pk.SPMM_EUNSUPPORTED
+    with pytest.raises(pk.SpmmError) as ei:
+        pk.spmm_build_tiles(rp, col, format=pk.SPMM_FORMAT_CSR, place=pk.SPMM_PLACE_PINNED_HOST)
+    assert ei.value.status == pk.SPMM_EUNSUPPORTED
