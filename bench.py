@@ -12,7 +12,10 @@ Tile variants: "learned" (default) lets the trained cost model pick each
 tile's variant for each k (one resident handle per distinct assignment, all
 built before the timed region); "plain" keeps the build default for every
 tile.  The plain step is timed as well and reported beside the learned one.
---compare adds every fixed variant and the exhaustive autotuner (per k).
+The format comparison (on by default, --no-compare skips it) times every
+fixed variant, the exhaustive autotuner and the learned choice per k on the
+same tiles, the untiled CSR baseline (V-csr), and the original row and
+column order.
 
 Printed (one JSON line on stdout): the metric, the roofline of the dominant
 kernel under the paper-tile byte model (16K x 16K tiles: A as SCSR, each
@@ -144,8 +147,8 @@ def main() -> int:
     ap.add_argument("--ks", default="1,2,4,8,16,32")
     ap.add_argument("--select", choices=["learned", "plain"], default="learned")
     ap.add_argument("--weights", default=None, help="cost-model weights (.npy)")
-    ap.add_argument("--compare", action="store_true",
-                    help="also time every fixed variant and the exhaustive autotuner per k")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="skip the format comparison (fixed variants, autotuner, learned, V-csr)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--tile-cols", type=int, default=0)
     ap.add_argument("--item-nnz", type=int, default=0)
@@ -156,10 +159,12 @@ def main() -> int:
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="run a plain device copy of this many GiB first (counter calibration)")
     ap.add_argument("--mode", default="spmm",
-                    help="spmm (default) | stream | colblocks | apps_directed | precision | apps | eigs | dense | sbm "
+                    help="spmm (default) | stream | semiext | colblocks | apps_directed | precision | apps | eigs | dense | sbm "
                          "(comma-separated)")
     ap.add_argument("--stream-kib", type=int, default=0, help="streamed mode: bytes per transfer group")
     ap.add_argument("--ring-depth", type=int, default=0, help="streamed mode: device ring slots")
+    ap.add_argument("--slab-rows", type=int, default=1 << 22,
+                    help="semiext mode: rows per block of the slab-wise build")
     ap.add_argument("--eig-blocks", default="1,2,4,8,16", help="eigs mode: block sizes")
     ap.add_argument("--nev", type=int, default=8, help="eigs mode: eigenpairs wanted")
     ap.add_argument("--eig-tol", type=float, default=1e-5, help="eigs mode: relative residual tolerance")
@@ -353,23 +358,36 @@ def main() -> int:
             compare["autotune_s"][str(k)] = round(time.perf_counter() - t0, 1)
             compare["autotune"][str(k)] = round(time_one(lambda: pk.spmm_run(hc, Xs[k], Ys[k], stream=stream)), 4)
             log(f"autotune k={k}: {compare['autotune'][str(k)]} ms ({compare['autotune_s'][str(k)]}s)")
-        # ablation: tiles over the original column order (no in-degree relabelling)
-        hk = pk.spmm_build_tiles(rp, col, tile_rows=args.tile_rows, tile_cols=args.tile_cols,
-                                 item_nnz=args.item_nnz, max_kc=args.max_kc, validate=False, keep_order=True)
-        compare["ablation_original_column_order"] = {str(k): round(time_one(
-            lambda k=k: pk.spmm_run(hk, Xs[k], Ys[k], stream=stream)), 4) for k in ks}
-        log(f"original column order: {compare['ablation_original_column_order']}")
-        hk.close()
+        # the untiled CSR baseline (V-csr): rows by length, columns in
+        # in-degree order, FP32 register sums
+        t0 = time.perf_counter()
+        hv = pk.spmm_build_tiles(rp, col, validate=False, format=pk.SPMM_FORMAT_CSR)
+        compare["csr_build_s"] = round(time.perf_counter() - t0, 1)
+        compare["v_csr"] = {str(k): round(time_one(
+            lambda k=k: pk.spmm_run(hv, Xs[k], Ys[k], stream=stream)), 4) for k in ks}
+        log(f"V-csr: {compare['v_csr']}")
+        hv.close()
+        # ablations: tiles over the original row order, and over the original
+        # row and column order (no relabelling at all)
+        for name, opt in (("ablation_original_row_order", dict(keep_row_order=True)),
+                          ("ablation_original_order", dict(keep_order=True))):
+            hk = pk.spmm_build_tiles(rp, col, tile_rows=args.tile_rows, tile_cols=args.tile_cols,
+                                     item_nnz=args.item_nnz, max_kc=args.max_kc, validate=False, **opt)
+            compare[name] = {str(k): round(time_one(
+                lambda k=k: pk.spmm_run(hk, Xs[k], Ys[k], stream=stream)), 4) for k in ks}
+            log(f"{name}: {compare[name]}")
+            hk.close()
         compare["learned"] = {}
         for k in ks:
             pk.spmm_select_learned(hc, params, k)
             compare["learned"][str(k)] = round(time_one(lambda: pk.spmm_run(hc, Xs[k], Ys[k], stream=stream)), 4)
         log(f"learned (same protocol): {compare['learned']}")
-        tot = {m: sum(d.values()) for m, d in compare.items() if not m.endswith("_s")}
+        tot = {m: sum(d.values()) for m, d in compare.items() if isinstance(d, dict) and not m.endswith("_s")}
         compare["sweep_gflops"] = {m: round(flop_step / (t * 1e-3) / 1e9, 1) for m, t in tot.items()}
         best_fixed = min(t for m, t in tot.items() if m.startswith("fixed_"))
         compare["learned_over_autotune"] = round(tot["learned"] / tot["autotune"], 4)
         compare["learned_over_best_fixed"] = round(tot["learned"] / best_fixed, 4)
+        compare["learned_over_v_csr"] = round(tot["learned"] / tot["v_csr"], 4)
         # re-select for the parity check below (Y of the last comparison run)
         for k in ks:
             pk.spmm_run(handle_of[k], Xs[k], Ys[k], stream=stream)
@@ -586,6 +604,86 @@ def run_other_modes(args, modes) -> int:
                    "payload_bytes": int(payload), "link_gbs_measured": round(link, 2),
                    "link_frac_min": min(v["link_frac"] for v in per_k.values()),
                    "per_k": per_k}
+            print(json.dumps(out), flush=True)
+            hd.close()
+            hs.close()
+        elif mode == "semiext":
+            # The semi-external configuration on one GPU: the tile store is
+            # built block by block (spmm_build_begin / append_rows / end)
+            # into pinned host memory and streamed to HBM for every SpMM; X is
+            # resident; Y either resident or streamed back to host memory.
+            # The same tiles placed in HBM give the in-HBM rate and the
+            # bit-identity check; sampled rows are checked against the oracle.
+            ks = [int(x) for x in args.ks.split(",")]
+            link = pinned_h2d_gbs()
+            log(f"pinned host-to-device copy: {link:.1f} GB/s")
+
+            def slab_build(place):
+                t0 = time.perf_counter()
+                h = pk.spmm_build_begin(n, keep_row_order=True, validate=False, place=place,
+                                        stream_kib=args.stream_kib, ring_depth=args.ring_depth)
+                for r0 in range(0, n, args.slab_rows):
+                    r1 = min(n, r0 + args.slab_rows)
+                    a, b = int(rp[r0]), int(rp[r1])
+                    pk.spmm_build_append_rows(h, r0, rp[r0:r1 + 1] - a, col[a:b])
+                    if (r0 // args.slab_rows) % 16 == 15 or r1 == n:
+                        log(f"slab-wise build ({'host' if place else 'device'}): rows {r1}/{n}")
+                pk.spmm_build_end(h)
+                return h, time.perf_counter() - t0
+
+            hs, t_bs = slab_build(pk.SPMM_PLACE_PINNED_HOST)
+            sst = pk.spmm_get_stats(hs)
+            payload = sst["blob_bytes"]
+            log(f"host-placed tiles built in {t_bs:.1f}s: {payload / nnz:.2f} B/nnz, {payload / 2**30:.1f} GiB")
+            hd, t_bd = slab_build(pk.SPMM_PLACE_DEVICE)
+            copy = torch.cuda.Stream(dev)
+            out_s = torch.cuda.Stream(dev)
+            rng = np.random.default_rng(7)
+            sel = np.unique(rng.integers(0, max(1, n // 32), 64) * 32)   # 64 random 32-row tile rows
+            sel = np.unique((sel[:, None] + np.arange(32)[None, :]).ravel())
+            sel = sel[sel < n]
+            per_k = {}
+            for k in ks:
+                X = torch.from_numpy(synth.uniform(n, k, seed=synth.SEED_X)).to(dev)
+                Yd = torch.empty((n, k), device=dev)
+                Ys = torch.empty((n, k), device=dev)
+                t_hbm = time_one(lambda: pk.spmm_run(hd, X, Yd, stream=stream))
+                t_str = time_one(lambda: pk.spmm_stream_run(hs, X, Ys, compute=stream, copy=copy))
+                torch.cuda.synchronize()
+                same = bool(torch.equal(Yd, Ys))
+                Yh = torch.empty((n, k), dtype=torch.float32).pin_memory()
+
+                def yhost():
+                    out_s.wait_stream(stream)
+                    pk.spmm_stream_run_yhost(hs, X, Yh, compute=stream, copy=copy, out=out_s)
+                    stream.wait_stream(out_s)
+                t_yh = time_one(yhost)
+                torch.cuda.synchronize()
+                same_yh = bool(torch.equal(Yd.cpu(), Yh))
+                ref = oracle.spmm_sel(rp, col, None, X.cpu().numpy(), sel)
+                err = oracle.frob_rel_err(Ys[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref)
+                per_k[str(k)] = {"hbm_ms": round(t_hbm, 3), "stream_ms": round(t_str, 3),
+                                 "stream_y_host_ms": round(t_yh, 3),
+                                 "stream_gflops": round(2.0 * nnz * k / (t_str * 1e-3) / 1e9, 2),
+                                 "hbm_gflops": round(2.0 * nnz * k / (t_hbm * 1e-3) / 1e9, 2),
+                                 "payload_gbs": round(payload / (t_str * 1e-3) / 1e9, 2),
+                                 "link_frac": round(payload / (t_str * 1e-3) / 1e9 / link, 4),
+                                 "stream_over_hbm": round(t_hbm / t_str, 4),
+                                 "y_identical_to_hbm": same, "y_host_identical_to_hbm": same_yh,
+                                 "sampled_rows": int(sel.size), "sampled_rel_err": err}
+                log(f"semiext k={k}: {per_k[str(k)]}")
+                del X, Yd, Ys, Yh
+            tot_s = sum(v["stream_ms"] for v in per_k.values())
+            out = {"mode": "semiext", "metric": "semi-external SpMM GFLOP/s (tiles built slab-wise into pinned host "
+                                                "memory, streamed per SpMM) and % of host-to-device link",
+                   "value": round(sum(2.0 * nnz * k for k in ks) / (tot_s * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                   "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": workload, "n": n, "nnz": nnz, "k": ks, "slab_rows": args.slab_rows,
+                              "row_order": "given", "column_order": "given",
+                              "stream_kib": args.stream_kib or 262144, "ring_depth": args.ring_depth or 3},
+                   "payload_bytes": int(payload), "payload_bytes_per_nnz": round(payload / nnz, 3),
+                   "build_s": {"host_placed": round(t_bs, 1), "device_placed": round(t_bd, 1)},
+                   "link_gbs_measured": round(link, 2), "per_k": per_k}
             print(json.dumps(out), flush=True)
             hd.close()
             hs.close()

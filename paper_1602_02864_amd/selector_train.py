@@ -2,9 +2,9 @@
 
     python -m paper_1602_02864_amd.selector_train [--out DIR] [--quick]
 
-Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 20-22 with graph
-seeds 11-16, directed and symmetrised, edge factors 8-44 -- never seed 1,
-the seed of the benchmark graphs.  Each graph is tiled with the library's
+Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 18-22 with graph
+seeds 11-15, 18 and 19, directed and symmetrised, edge factors 8-44 --
+never seed 1 (the benchmark graphs) or 17 (the held-out graphs).  Each graph is tiled with the library's
 default geometry (32-row tile rows, 65536-column strips).  For every graph,
 column count k and X type, spmm_selector_collect times each variant on
 every bucket of similar tiles; a training row is one tile: its 8 features
@@ -40,8 +40,8 @@ import paper_1602_02864_amd as pk  # noqa: E402
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.npy")
 
 # (scale, edge factor, graph seed, symmetrise)
-TRAIN_GRAPHS = [(20, 16, 11, False), (21, 44, 12, False), (22, 8, 13, True),
-                (21, 28, 14, True), (22, 44, 15, False)]
+TRAIN_GRAPHS = [(18, 16, 18, False), (19, 8, 19, True), (20, 16, 11, False), (21, 44, 12, False),
+                (22, 8, 13, True), (21, 28, 14, True), (22, 44, 15, False)]
 HELD_OUT = (22, 32, 17, False)
 QUICK_GRAPHS = [(16, 16, 11, False), (17, 8, 13, True)]
 QUICK_HELD_OUT = (17, 16, 17, False)

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("keep", [False, True])
 def test_csr_format_matches_oracle(keep):
-    rp, col = synth.rmat_csr(16, 16, seed=1)
+    rp, col = synth.rmat_csr(16, 16, seed=1, symmetrize=True)
     n = rp.shape[0] - 1
     assert np.diff(rp).max() > 8192          # some rows are split into pieces
     h = pk.spmm_build_tiles(rp, col, format=pk.SPMM_FORMAT_CSR, keep_order=keep)
