@@ -245,6 +245,27 @@ spmm_status_t spmm_run(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_
                        const float* col_scale, float* Y, int64_t ldy, hipStream_t s);
 
 /*
+ * spmm_run for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, arithmetic and result as spmm_run (bit-identical), with
+ * two preconditions and no allocation of any kind:
+ *   - the handle is built with keep_order = 1 (columns and rows in the given
+ *     order), so X is read in place: SPMM_EUNSUPPORTED otherwise;
+ *   - its tiles are already on the device, i.e. spmm_run has been called on
+ *     the handle once: SPMM_ESTATE otherwise.
+ * The launch's scratch (split-row partial sums, their counters, X's column
+ * maxima and fixed-point exponents) lives in a static device array of
+ * 16 MiB that each GPU the library runs on holds until the process ends; a
+ * handle needing more (about n_parts * 32 * 8 bytes, reported by
+ * spmm_get_stats) gets SPMM_EINVAL.  All calls on one GPU share that array:
+ * calls that overlap on one GPU race (serialise them, e.g. on one stream).
+ * Asynchronous on s.  Errors: SPMM_EINVAL, SPMM_ESTATE, SPMM_EUNSUPPORTED,
+ * SPMM_EHIP.
+ */
+spmm_status_t spmm_run_static(spmm_handle_t h, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
+                              const float* col_scale, float* Y, int64_t ldy, hipStream_t s);
+
+/*
  * Quantise X for the reduced-precision SpMM paths (not in the paper; halves
  * or quarters the X bytes every SpMM gathers).
  *   X     : device FP32, n x k, row stride ldx >= k.

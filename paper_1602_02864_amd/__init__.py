@@ -132,6 +132,8 @@ def load_library():
     L.spmm_destroy.argtypes = [vp]
     L.spmm_run.restype = i32
     L.spmm_run.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp]
+    L.spmm_run_static.restype = i32
+    L.spmm_run_static.argtypes = [vp, vp, i32, i64, i32, vp, vp, i64, vp]
     L.spmm_quantize_x.restype = i32
     L.spmm_quantize_x.argtypes = [vp, i64, i32, i64, i32, vp, i64, vp, ctypes.c_uint32, vp]
     L.spmm_stream_run.restype = i32
@@ -350,6 +352,23 @@ def spmm_run(h: Handle, X, Y, k: int | None = None, ldx: int | None = None, dtyp
     st = L.spmm_run(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
                     int(ldy), _stream(stream, X))
     _check(st, "spmm_run")
+
+
+def spmm_run_static(h: Handle, X, Y, k: int | None = None, ldx: int | None = None, dtype: int | None = None,
+                    col_scale=None, ldy: int | None = None, stream=None):
+    """spmm_run without device allocation (static scratch; see spmm.h):
+    the handle must keep the given order and be on the device already."""
+    _check_tensors(X, Y, dtype)
+    L = load_library()
+    if k is None:
+        k = X.shape[1]
+    if ldx is None:
+        ldx = X.stride(0)
+    if ldy is None:
+        ldy = Y.stride(0)
+    st = L.spmm_run_static(h.ptr, _ptr(X), int(k), int(ldx), _xdtype(X, dtype), _ptr(col_scale), _ptr(Y),
+                           int(ldy), _stream(stream, X))
+    _check(st, "spmm_run_static")
 
 
 SPMM_QUANT_SCALES_GIVEN = 1

@@ -302,6 +302,39 @@ spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int
     return zero_empty_rows(H, Y, ldy, k, s);
 }
 
+// spmm_run's work on a device-placed handle whose columns keep the given
+// order (X is read in place), with its scratch given by the caller: part
+// (split-row partial sums), count (their counters, zero on entry), colmax
+// and fexp (64 entries each).  Allocates nothing.
+spmm_status_t run_device_scratch(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt,
+                                 const float* col_scale, float* Y, int64_t ldy, hipStream_t s, int64_t* part,
+                                 uint32_t* count, uint32_t* colmax, int32_t* fexp) {
+    hipError_t e = spmm::launch_prepare_x(X, dt, ldx, k, nullptr, H.n_cols, nullptr, ldx, H.max_row_l1, colmax,
+                                          fexp, s);
+    if (e != hipSuccess) return hip_fail(e, "X preparation launch");
+    spmm::RunArgs a{};
+    a.X = X;
+    a.k = k;
+    a.ldx = ldx;
+    a.fexp = fexp;
+    a.dtype = dt;
+    a.col_scale = col_scale;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.stream = s;
+    a.blob = static_cast<const uint8_t*>(H.d_blob);
+    a.blob_bias = 0;
+    a.items = H.d_items;
+    a.n_items = (uint32_t)H.enc.items.size();
+    a.combine = H.d_combine;
+    a.n_combine = (uint32_t)H.enc.combine.size();
+    a.count = count;
+    a.part = part;
+    a.rmap = H.d_row_old;
+    if ((e = spmm::launch_spmm(H, a)) != hipSuccess) return hip_fail(e, "kernel launch");
+    return zero_empty_rows(H, Y, ldy, k, s);
+}
+
 // The SpMM launches alone, with fixed-point exponents already in fexp and X
 // in the handle's column order (used to time buckets of tiles).
 spmm_status_t launch_items_only(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt,

@@ -32,6 +32,10 @@ spmm_status_t prepare_device(spmm::Handle& H);
 // exponents, SpMM launches.
 spmm_status_t run_device(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt, const float* col_scale,
                          float* Y, int64_t ldy, hipStream_t s, bool x_in_handle_order);
+// spmm_run's work with caller-given scratch (see abi.cpp); allocates nothing.
+spmm_status_t run_device_scratch(spmm::Handle& H, const void* X, int k, int64_t ldx, int dt,
+                                 const float* col_scale, float* Y, int64_t ldy, hipStream_t s, int64_t* part,
+                                 uint32_t* count, uint32_t* colmax, int32_t* fexp);
 // Argument checks shared by the run entry points.
 spmm_status_t check_run_args(const spmm::Handle& H, const void* X, int k, int64_t ldx, spmm_xdtype_t dt,
                              const float* col_scale, const float* Y, int64_t ldy);
