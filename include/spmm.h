@@ -174,7 +174,11 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
  *     - rows are taken by descending out-degree within each appended block
  *       (together with the rows still untiled from the block before), unless
  *       keep_row_order or keep_order is set;
- *     - transpose is not supported (SPMM_EUNSUPPORTED).
+ *     - transpose is not supported (SPMM_EUNSUPPORTED);
+ *     - every tile takes fixed_variant (HYBRID if it is -1): the per-tile
+ *       selectors (spmm_tile_features, spmm_get_variants, spmm_set_variants,
+ *       spmm_selector_collect, spmm_autotune, spmm_select_learned) return
+ *       SPMM_EUNSUPPORTED on such a handle, which keeps no per-tile store.
  *   Errors: SPMM_EINVAL (shape, options), SPMM_EUNSUPPORTED, SPMM_ENOMEM.
  *
  * spmm_build_append_rows: rows [row0, row0 + nrows), in order: row0 must be
@@ -186,8 +190,10 @@ spmm_status_t spmm_build_tiles(int64_t n_rows, int64_t n_cols, const int64_t* ro
  *     values        : host float or NULL; NULL for every block or for none
  *                     (the first call decides).
  *   The arrays are read during the call only; the caller may free them on
- *   return.  Whole tile rows are tiled at once; up to tile_rows - 1 rows are
- *   copied and kept for the next call.  On error the handle must be
+ *   return.  Whole tile rows are tiled and encoded at once, and their tiles
+ *   released: host memory holds the encoded payload plus one block's tiles,
+ *   never a per-tile store of the whole matrix.  Up to tile_rows - 1 rows
+ *   are copied and kept for the next call.  On error the handle must be
  *   destroyed.  Errors: SPMM_EINVAL (order, CSR), SPMM_ESTATE (not being
  *   built), SPMM_ENOMEM.
  *

@@ -607,8 +607,7 @@ spmm_status_t spmm_build_end(spmm_handle_t h) {
         std::string err;
         spmm_status_t st = spmm::build_finish_rows(H, err);
         if (st != SPMM_OK) return fail(st, err);
-        if (H.fixed_variant >= 0) std::fill(H.variant.begin(), H.variant.end(), (uint8_t)H.fixed_variant);
-        if ((st = spmm::encode(H, err)) != SPMM_OK) return fail(st, err);
+        if ((st = spmm::flush_slabs(H, err)) != SPMM_OK) return fail(st, err);
         H.building = false;
         return SPMM_OK;
     } catch (const std::bad_alloc&) {
@@ -1044,7 +1043,7 @@ spmm_status_t spmm_get_stats(spmm_handle_t h, spmm_stats_t* out) {
     s.tile_rows = H.h;
     s.tile_cols = H.w;
     s.n_slabs = H.n_slabs;
-    s.n_tiles = H.tiles.size();
+    s.n_tiles = H.n_tiles_total;
     s.sum_nnr = H.sum_nnr;
     s.sum_nnc = H.sum_nnc;
     s.n_items = H.enc.items.size();

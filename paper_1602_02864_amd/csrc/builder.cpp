@@ -163,6 +163,7 @@ spmm_status_t tile_rows(Handle& H, const RowRef* rows, int64_t count, std::strin
     if (H.slab_tiles.empty()) H.slab_tiles.push_back(0);
     for (uint64_t s = 0; s < ns; ++s) H.slab_tiles.push_back(H.slab_tiles.back() + ntile[s + 1]);
     const uint64_t T = H.slab_tiles.back();
+    const uint64_t lbase = s_first - H.slab_base;   // local index of the first new slab
     try {
         // grow by at least a quarter, so that a build in many blocks does
         // not reallocate per block (and never doubles its peak footprint)
@@ -173,7 +174,7 @@ spmm_status_t tile_rows(Handle& H, const RowRef* rows, int64_t count, std::strin
         H.tiles.resize(T);
         grow(H.ent, ent0 + bnnz);
         if (hv) grow(H.val, ent0 + bnnz);
-        H.variant.resize(T, (uint8_t)SPMM_VAR_HYBRID);
+        H.variant.resize(T, (uint8_t)(H.fixed_variant >= 0 ? H.fixed_variant : SPMM_VAR_HYBRID));
         if (H.row_relabel) {
             grow(H.row_old, (size_t)(H.n_tiled_rows + count));
             for (int64_t r = 0; r < count; ++r) H.row_old[(size_t)(H.n_tiled_rows + r)] = (int32_t)rows[r].row;
@@ -202,7 +203,7 @@ spmm_status_t tile_rows(Handle& H, const RowRef* rows, int64_t count, std::strin
                 }
             std::sort(used.begin(), used.end());
             uint64_t e = ent0 + sbase[s];
-            uint64_t t = H.slab_tiles[gs];
+            uint64_t t = H.slab_tiles[lbase + s];
             for (uint32_t J : used) {
                 Tile& tl = H.tiles[t++];
                 tl.ent_begin = e;
@@ -225,7 +226,7 @@ spmm_status_t tile_rows(Handle& H, const RowRef* rows, int64_t count, std::strin
             if (cmap) {
                 // relabelled columns arrive unordered within a row: sort each
                 // tile's entries by (row, column), carrying the values along
-                for (uint64_t ti = H.slab_tiles[gs]; ti < H.slab_tiles[gs + 1]; ++ti) {
+                for (uint64_t ti = H.slab_tiles[lbase + s]; ti < H.slab_tiles[lbase + s + 1]; ++ti) {
                     const Tile& tl = H.tiles[ti];
                     uint32_t* E = H.ent.data() + tl.ent_begin;
                     if (!hv) {
@@ -242,7 +243,7 @@ spmm_status_t tile_rows(Handle& H, const RowRef* rows, int64_t count, std::strin
                     }
                 }
             }
-            for (uint64_t ti = H.slab_tiles[gs]; ti < H.slab_tiles[gs + 1]; ++ti) {
+            for (uint64_t ti = H.slab_tiles[lbase + s]; ti < H.slab_tiles[lbase + s + 1]; ++ti) {
                 Tile& tl = H.tiles[ti];
                 const uint32_t* E = H.ent.data() + tl.ent_begin;
                 uint32_t nnr = 0, maxr = 0, single = 0, run = 0, nnc = 0;
@@ -271,7 +272,7 @@ spmm_status_t tile_rows(Handle& H, const RowRef* rows, int64_t count, std::strin
         tot_nnr += my_nnr;
         tot_nnc += my_nnc;
     });
-    (void)t_first;
+    H.n_tiles_total += T - t_first;
     H.sum_nnr += tot_nnr;
     H.sum_nnc += tot_nnc;
     H.n_slabs += ns;
@@ -525,6 +526,23 @@ spmm_status_t build_csr(Handle& H, const int64_t* row_ptr, const int32_t* col, b
     return SPMM_OK;
 }
 
+// Encode the tile rows cut since the last flush, append them to the
+// encoding, and release their canonical tiles: a slab-wise build holds one
+// block's tiles at a time.
+spmm_status_t flush_slabs(Handle& H, std::string& err) {
+    if (H.n_slabs == H.slab_base) return SPMM_OK;
+    spmm_status_t st = encode_range(H, H.slab_base, H.n_slabs, err);
+    if (st != SPMM_OK) return st;
+    H.slab_base = H.n_slabs;
+    std::vector<Tile>().swap(H.tiles);
+    std::vector<uint32_t>().swap(H.ent);
+    std::vector<float>().swap(H.val);
+    std::vector<uint8_t>().swap(H.variant);
+    std::vector<uint64_t>().swap(H.slab_tiles);
+    H.canonical = false;
+    return SPMM_OK;
+}
+
 spmm_status_t build_append(Handle& H, int64_t row0, int64_t nr, const int64_t* rp, const int32_t* col,
                            const float* val, bool validate, std::string& err) {
     if (row0 != H.next_row || nr < 0 || row0 + nr > H.n_rows) {
@@ -544,7 +562,7 @@ spmm_status_t build_append(Handle& H, int64_t row0, int64_t nr, const int64_t* r
     if ((st = tile_block(H, row0, nr, rp, col, val, false, err)) != SPMM_OK) return st;
     H.nnz += rp[nr];
     H.next_row = row0 + nr;
-    return SPMM_OK;
+    return flush_slabs(H, err);
 }
 
 spmm_status_t build_finish_rows(Handle& H, std::string& err) {
@@ -720,7 +738,7 @@ void encode_slab(const Handle& H, uint64_t s, ChunkOut& out, Scratch& S) {
     const uint32_t C = H.item_nnz;
     const int64_t r0 = (int64_t)s * H.h;
     const uint32_t nr = (uint32_t)std::min<int64_t>(H.h, H.n_tiled_rows - r0);
-    const uint64_t t0 = H.slab_tiles[s], t1 = H.slab_tiles[s + 1];
+    const uint64_t t0 = H.slab_tiles[s - H.slab_base], t1 = H.slab_tiles[s - H.slab_base + 1];
     S.rdeg.assign(nr, 0);
     S.cursor.resize(t1 - t0);
     for (uint64_t t = t0; t < t1; ++t) {
@@ -831,7 +849,12 @@ std::vector<Handle::Group> make_groups(const Encoded& E, uint64_t stream_bytes, 
 }
 
 spmm_status_t encode(Handle& H, std::string& err) {
-    const uint64_t S = H.n_slabs;
+    H.enc = Encoded{};
+    return encode_range(H, H.slab_base, H.n_slabs, err);
+}
+
+spmm_status_t encode_range(Handle& H, uint64_t s0, uint64_t s1, std::string& err) {
+    const uint64_t S = s1 - s0;
     const uint64_t chunk = 256;
     const uint64_t nchunks = (S + chunk - 1) / chunk;
     std::vector<ChunkOut> outs(nchunks);
@@ -839,17 +862,20 @@ spmm_status_t encode(Handle& H, std::string& err) {
         parallel_for(nchunks, H.threads, 1, [&](uint64_t a, uint64_t b) {
             Scratch sc;
             for (uint64_t c = a; c < b; ++c) {
-                uint64_t s1 = std::min(S, (c + 1) * chunk);
-                for (uint64_t s = c * chunk; s < s1; ++s) encode_slab(H, s, outs[c], sc);
+                const uint64_t e1 = s0 + std::min(S, (c + 1) * chunk);
+                for (uint64_t s = s0 + c * chunk; s < e1; ++s) encode_slab(H, s, outs[c], sc);
             }
         });
     } catch (const std::bad_alloc&) {
         err = "out of host memory while encoding tiles";
         return SPMM_ENOMEM;
     }
-    Encoded E;
-    std::vector<uint64_t> item_off(nchunks + 1, 0), byte_off(nchunks + 1, 0), comb_off(nchunks + 1, 0);
-    std::vector<uint32_t> part_off(nchunks + 1, 0);
+    Encoded& E = H.enc;
+    // offsets of this range's output in the accumulated encoding
+    const uint64_t item0 = E.items.size(), byte0 = E.blob.size(), comb0 = E.combine.size();
+    const uint64_t part0 = E.n_parts;
+    std::vector<uint64_t> item_off(nchunks + 1, item0), byte_off(nchunks + 1, byte0), comb_off(nchunks + 1, comb0);
+    std::vector<uint64_t> part_off(nchunks + 1, part0);
     for (uint64_t c = 0; c < nchunks; ++c) {
         item_off[c + 1] = item_off[c] + outs[c].items.size();
         byte_off[c + 1] = byte_off[c] + outs[c].blob.size();
@@ -859,6 +885,10 @@ spmm_status_t encode(Handle& H, std::string& err) {
             E.variant_tiles[v] += outs[c].vt[v];
             E.variant_nnz[v] += outs[c].vn[v];
         }
+    }
+    if (part_off[nchunks] > INT32_MAX) {
+        err = "too many split-row pieces for 32-bit slot indices";
+        return SPMM_EUNSUPPORTED;
     }
     try {
         E.items.resize(item_off[nchunks]);
@@ -885,8 +915,8 @@ spmm_status_t encode(Handle& H, std::string& err) {
             }
             for (size_t i = 0; i < o.combine.size(); ++i) {
                 CombineDesc cd = o.combine[i];
-                cd.part_begin += part_off[c];
-                cd.part_end += part_off[c];
+                cd.part_begin += (uint32_t)part_off[c];
+                cd.part_end += (uint32_t)part_off[c];
                 E.combine[comb_off[c] + i] = cd;
             }
             std::vector<uint8_t>().swap(o.blob);
@@ -894,9 +924,12 @@ spmm_status_t encode(Handle& H, std::string& err) {
     });
     E.n_parts = part_off[nchunks];
     H.blob_bytes = E.blob.size();
-    H.enc = std::move(E);
     return SPMM_OK;
 }
+
+}  // namespace spmm
+
+namespace spmm {
 
 void tile_features(const Handle& H, int k, int xbytes, float* out) {
     parallel_for(H.tiles.size(), H.threads, 1 << 14, [&](uint64_t a, uint64_t b) {

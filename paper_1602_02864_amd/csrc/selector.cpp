@@ -56,6 +56,17 @@ spmm_status_t reencode(spmm::Handle& H) {
     return st == SPMM_OK ? st : fail(st, err);
 }
 
+// Variant selection works on the canonical tile store: a tile-format
+// handle built in one pass.  A slab-wise build encodes each block as it is
+// cut and keeps only the encoding.
+spmm_status_t need_tiles(spmm_handle_t h) {
+    if (h->H.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "variants are chosen per tile");
+    if (!h->H.canonical)
+        return fail(SPMM_EUNSUPPORTED,
+                    "a slab-wise build keeps no per-tile store; choose the variant with fixed_variant");
+    return SPMM_OK;
+}
+
 // Bucket of a feature cell: size class floor(f0) (0..15), skew class of f5
 // (< 1, < 2, < 3, >= 3) and whether most non-empty rows hold one entry.
 uint32_t feature_cell(const float* f) {
@@ -102,8 +113,9 @@ uint32_t make_buckets(const std::vector<float>& feat, uint64_t T, uint32_t min_t
 }
 
 // A handle holding only the listed tiles of H (in H's order), their tile
-// rows renumbered consecutively so that the sub-matrix has no empty slabs.
-void make_subset(const spmm::Handle& H, const std::vector<uint64_t>& sel, spmm::Handle& S) {
+// rows renumbered consecutively so that the sub-matrix has no empty slabs;
+// the whole list is repeated `copies` times as further tile rows.
+void make_subset(const spmm::Handle& H, const std::vector<uint64_t>& sel, spmm::Handle& S, uint32_t copies) {
     S.n_cols = H.n_cols;
     S.h = H.h;
     S.w = H.w;
@@ -117,35 +129,45 @@ void make_subset(const spmm::Handle& H, const std::vector<uint64_t>& sel, spmm::
     S.max_kc = H.max_kc;
     S.stage_bytes = H.stage_bytes;
     S.relabel = false;
-    uint64_t nnz = 0;
-    for (uint64_t t : sel) nnz += H.tiles[t].nnz;
+    uint64_t nnz1 = 0;
+    for (uint64_t t : sel) nnz1 += H.tiles[t].nnz;
+    const uint64_t nnz = nnz1 * copies;
     S.ent.resize(nnz);
     if (H.has_val) S.val.resize(nnz);
-    S.tiles.resize(sel.size());
+    S.tiles.resize(sel.size() * copies);
     S.slab_tiles.clear();
     S.slab_tiles.push_back(0);
-    uint64_t pos = 0;
-    uint32_t prev_slab = UINT32_MAX;
-    for (size_t i = 0; i < sel.size(); ++i) {
-        const spmm::Tile& src = H.tiles[sel[i]];
-        if (src.slab != prev_slab) {
-            if (i) S.slab_tiles.push_back(i);
-            prev_slab = src.slab;
+    uint64_t pos = 0, i = 0;
+    for (uint32_t c = 0; c < copies; ++c) {
+        uint32_t prev_slab = UINT32_MAX;
+        for (size_t j = 0; j < sel.size(); ++j, ++i) {
+            const spmm::Tile& src = H.tiles[sel[j]];
+            if (src.slab != prev_slab) {
+                if (i) S.slab_tiles.push_back(i);
+                prev_slab = src.slab;
+            }
+            spmm::Tile d = src;
+            d.slab = (uint32_t)(S.slab_tiles.size() - 1);
+            d.ent_begin = pos;
+            std::memcpy(&S.ent[pos], &H.ent[src.ent_begin], sizeof(uint32_t) * src.nnz);
+            if (H.has_val) std::memcpy(&S.val[pos], &H.val[src.ent_begin], sizeof(float) * src.nnz);
+            pos += src.nnz;
+            S.tiles[i] = d;
         }
-        spmm::Tile d = src;
-        d.slab = (uint32_t)(S.slab_tiles.size() - 1);
-        d.ent_begin = pos;
-        std::memcpy(&S.ent[pos], &H.ent[src.ent_begin], sizeof(uint32_t) * src.nnz);
-        if (H.has_val) std::memcpy(&S.val[pos], &H.val[src.ent_begin], sizeof(float) * src.nnz);
-        pos += src.nnz;
-        S.tiles[i] = d;
     }
-    S.slab_tiles.push_back(sel.size());
+    S.slab_tiles.push_back(S.tiles.size());
     S.n_slabs = S.slab_tiles.size() - 1;
     S.n_rows = (int64_t)S.n_slabs * H.h;
     S.n_tiled_rows = S.n_rows;
     S.nnz = (int64_t)nnz;
 }
+
+// A bucket is timed with at least this many work items (wavefronts) in
+// flight, repeating its tiles if needed: a handful of items would leave the
+// GPU nearly idle and time each variant's latency rather than its cost
+// inside a full SpMM.  The repetition stops at kFillMaxNnz entries.
+constexpr uint64_t kFillItems = 2048;
+constexpr uint64_t kFillMaxNnz = uint64_t(1) << 22;
 
 // Median of the per-launch times of reps launches of the sub-handle.
 spmm_status_t time_launches(spmm::Handle& S, const void* X, int k, int dt, const float* cs, float* Y,
@@ -190,22 +212,13 @@ spmm_status_t collect(spmm::Handle& H, int k, int dt, const spmm_tune_opts* opts
     if (!nb) return SPMM_OK;
     std::vector<std::vector<uint64_t>> members(nb);
     for (uint64_t t = 0; t < T; ++t) members[bucket[t]].push_back(t);
-    uint64_t max_slabs = 0;
-    for (const auto& m : members) {
-        uint64_t c = 0;
-        uint32_t prev = UINT32_MAX;
-        for (uint64_t t : m)
-            if (H.tiles[t].slab != prev) ++c, prev = H.tiles[t].slab;
-        max_slabs = std::max(max_slabs, c);
-    }
     DevBufs B;
     B.sync_on(s);
     const size_t esz = (size_t)xbytes_of(dt);
     void* X = B.get<uint8_t>((size_t)std::max<int64_t>(H.n_cols, 1) * k * esz);
-    float* Y = B.get<float>((size_t)max_slabs * H.h * k);
     int32_t* fexp = B.get<int32_t>(64);
     float* cs = B.get<float>(64);
-    if (!X || !Y || !fexp || !cs) return fail(SPMM_ENOMEM, "hipMalloc(timing buffers) failed");
+    if (!X || !fexp || !cs) return fail(SPMM_ENOMEM, "hipMalloc(timing buffers) failed");
     hipError_t e;
     // X = 0 (every encoding's zero) with exponent 0: the kernels take the
     // same path as for any finite X, and FP8 scales of 1 keep Y finite.
@@ -216,8 +229,25 @@ spmm_status_t collect(spmm::Handle& H, int k, int dt, const spmm_tune_opts* opts
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return hip_fail(e, "timing buffer set-up");
     for (uint32_t b = 0; b < nb; ++b) {
+        // copies of the bucket's tiles so that a launch has kFillItems items
+        uint32_t copies = 1;
+        {
+            spmm::Handle S1;
+            make_subset(H, members[b], S1, 1);
+            S1.variant.assign(S1.tiles.size(), (uint8_t)SPMM_VAR_HYBRID);
+            spmm_status_t st = reencode(S1);
+            if (st != SPMM_OK) return st;
+            const uint64_t items = std::max<uint64_t>(S1.enc.items.size(), 1);
+            const uint64_t by_items = (kFillItems + items - 1) / items;
+            const uint64_t by_nnz = std::max<uint64_t>(1, kFillMaxNnz / std::max<uint64_t>(S1.nnz, 1));
+            copies = (uint32_t)std::max<uint64_t>(1, std::min(by_items, by_nnz));
+        }
         spmm::Handle S;
-        make_subset(H, members[b], S);
+        make_subset(H, members[b], S, copies);
+        DevBufs BY;
+        BY.sync_on(s);
+        float* Y = BY.get<float>((size_t)S.n_rows * k);
+        if (!Y) return fail(SPMM_ENOMEM, "hipMalloc(timing buffers) failed");
         for (int v = 0; v < SPMM_NUM_VARIANTS; ++v) {
             S.variant.assign(S.tiles.size(), (uint8_t)v);
             spmm_status_t st = reencode(S);
@@ -226,7 +256,7 @@ spmm_status_t collect(spmm::Handle& H, int k, int dt, const spmm_tune_opts* opts
                 st = time_launches(S, X, k, dt, dt == SPMM_X_FP8_E4M3 ? cs : nullptr, Y, fexp, reps, s, ms);
             free_device(S);
             if (st != SPMM_OK) return st;
-            ns[(size_t)b * SPMM_NUM_VARIANTS + v] = ms * 1.0e6f / (float)members[b].size();
+            ns[(size_t)b * SPMM_NUM_VARIANTS + v] = ms * 1.0e6f / ((float)members[b].size() * (float)copies);
         }
     }
     return SPMM_OK;
@@ -238,6 +268,7 @@ extern "C" {
 
 spmm_status_t spmm_tile_features(spmm_handle_t h, int k, spmm_xdtype_t dt, float* feat) {
     if (spmm_status_t rs = check_ready(h)) return rs;
+    if (spmm_status_t rs = need_tiles(h)) return rs;
     if (!h || (!feat && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
     if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
     spmm::tile_features(h->H, k, xbytes_of(dt), feat);
@@ -246,6 +277,7 @@ spmm_status_t spmm_tile_features(spmm_handle_t h, int k, spmm_xdtype_t dt, float
 
 spmm_status_t spmm_get_variants(spmm_handle_t h, uint8_t* variant) {
     if (spmm_status_t rs = check_ready(h)) return rs;
+    if (spmm_status_t rs = need_tiles(h)) return rs;
     if (!h || (!variant && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
     if (!h->H.variant.empty()) std::memcpy(variant, h->H.variant.data(), h->H.variant.size());
     return SPMM_OK;
@@ -254,6 +286,7 @@ spmm_status_t spmm_get_variants(spmm_handle_t h, uint8_t* variant) {
 spmm_status_t spmm_set_variants(spmm_handle_t h, const uint8_t* variant) {
     try {
         if (spmm_status_t rs = check_ready(h)) return rs;
+        if (spmm_status_t rs = need_tiles(h)) return rs;
         if (!variant && !h->H.tiles.empty()) return fail(SPMM_EINVAL, "NULL argument");
         spmm::Handle& H = h->H;
         for (size_t t = 0; t < H.tiles.size(); ++t)
@@ -269,7 +302,7 @@ spmm_status_t spmm_selector_collect(spmm_handle_t h, int k, spmm_xdtype_t dt, co
                                     uint32_t* bucket, uint32_t* n_buckets, float* ns, hipStream_t s) {
     try {
         if (spmm_status_t rs = check_ready(h)) return rs;
-        if (h->H.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "variants are chosen per tile");
+        if (spmm_status_t rs = need_tiles(h)) return rs;
         if (!n_buckets || !ns || (!bucket && !h->H.tiles.empty())) return fail(SPMM_EINVAL, "NULL argument");
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         if (h->H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "bucket timing needs device placement");
@@ -291,7 +324,7 @@ spmm_status_t spmm_autotune(spmm_handle_t h, int k, spmm_xdtype_t dt, const spmm
                             uint32_t* n_buckets, float* ns, hipStream_t s) {
     try {
         if (spmm_status_t rs = check_ready(h)) return rs;
-        if (h->H.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "variants are chosen per tile");
+        if (spmm_status_t rs = need_tiles(h)) return rs;
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         spmm::Handle& H = h->H;
         if (H.place != SPMM_PLACE_DEVICE) return fail(SPMM_ESTATE, "bucket timing needs device placement");
@@ -468,7 +501,7 @@ spmm_status_t spmm_selector_train(const float* feat, const float* target, const 
 spmm_status_t spmm_select_learned(spmm_handle_t h, const float* params, int k, spmm_xdtype_t dt) {
     try {
         if (spmm_status_t rs = check_ready(h)) return rs;
-        if (h->H.format != SPMM_FORMAT_TILES) return fail(SPMM_EUNSUPPORTED, "variants are chosen per tile");
+        if (spmm_status_t rs = need_tiles(h)) return rs;
         if (!params) return fail(SPMM_EINVAL, "NULL argument");
         if (k < 1 || k > 64 || !valid_dt(dt)) return fail(SPMM_EINVAL, "need 1 <= k <= 64 and a known dt");
         spmm::Handle& H = h->H;

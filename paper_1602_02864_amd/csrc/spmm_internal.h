@@ -160,6 +160,14 @@ struct Handle {
     int32_t* d_row_old = nullptr;      // device copy of row_old
     void* d_nmf_ws = nullptr;          // NMF workspace (kept between calls)
     size_t nmf_ws_bytes = 0;
+    // The canonical tile store (tiles, ent, val, variant, slab_tiles) holds
+    // tile rows slab_base .. n_slabs-1.  A one-shot build keeps all of them
+    // (canonical = true: the selector can re-encode); a slab-wise build
+    // encodes each block of tile rows as it is cut and drops it
+    // (canonical = false: only the encoded payload remains).
+    bool canonical = true;
+    uint64_t slab_base = 0;
+    uint64_t n_tiles_total = 0;        // tiles cut so far, dropped or not
     // slab-wise build state: rows appended so far, rows not yet tiled (a
     // partial tile row), rows without entries (zero-filled)
     bool building = false;
@@ -232,9 +240,12 @@ spmm_status_t build_append(Handle& H, int64_t row0, int64_t nr, const int64_t* r
                            const float* val, bool validate, std::string& err);
 // Tile the rows still pending and complete the row map.
 spmm_status_t build_finish_rows(Handle& H, std::string& err);
+spmm_status_t flush_slabs(Handle& H, std::string& err);
 // The untiled CSR store of a binary matrix (format SPMM_FORMAT_CSR).
 spmm_status_t build_csr(Handle& H, const int64_t* row_ptr, const int32_t* col, bool validate, std::string& err);
 spmm_status_t encode(Handle& H, std::string& err);
+// Encode tile rows [s0, s1) of the canonical store and append them to H.enc.
+spmm_status_t encode_range(Handle& H, uint64_t s0, uint64_t s1, std::string& err);
 // CSR of the transpose of an n_rows x n_cols CSR (rows ascending within each
 // row of the result; duplicates kept), with range checks on the input.
 spmm_status_t transpose_csr(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr, const int32_t* col,

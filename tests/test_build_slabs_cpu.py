@@ -105,3 +105,22 @@ def test_slab_build_call_order_enforced():
     with pytest.raises(pk.SpmmError) as ei:
         pk.spmm_build_begin(n, transpose=True)
     assert ei.value.status == pk.SPMM_EUNSUPPORTED
+
+
+def test_slab_build_keeps_no_tile_store():
+    """Each block is encoded as it is cut and its tiles are dropped: every
+    tile carries fixed_variant (HYBRID by default), and the per-tile
+    selectors refuse the handle."""
+    rp, col = synth.rmat_csr(12, 8, seed=25)
+    for fv, want in ((-1, pk.SPMM_VAR_HYBRID), (pk.SPMM_VAR_COO, pk.SPMM_VAR_COO)):
+        h = _slab_build(rp, col, None, [500, 3000], fixed_variant=fv)
+        st = pk.spmm_get_stats(h)
+        assert st["variant_tiles"][want] == st["n_tiles"] > 0
+        for call in (lambda: pk.spmm_tile_features(h, 4), lambda: pk.spmm_get_variants(h),
+                     lambda: pk.spmm_select_learned(h, np.zeros(pk.SPMM_MLP_PARAMS, np.float32), 4)):
+            with pytest.raises(pk.SpmmError) as ei:
+                call()
+            assert ei.value.status == pk.SPMM_EUNSUPPORTED
+        drp, dcol = pk.spmm_decode_tiles(h, col.shape[0])
+        assert np.array_equal(drp, rp) and np.array_equal(dcol, col)
+        h.close()
