@@ -2,8 +2,8 @@
 
     python -m paper_1602_02864_amd.selector_train [--out DIR] [--quick]
 
-Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 18-22 with graph
-seeds 11-15, 18 and 19, directed and symmetrised, edge factors 8-44 --
+Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 18-24 with graph
+seeds 11-15, 18, 19 and 21, directed and symmetrised, edge factors 8-44 --
 never seed 1 (the benchmark graphs) or 17 (the held-out graphs).  Each graph is tiled with the library's
 default geometry (32-row tile rows, 65536-column strips).  For every graph,
 column count k and X type, spmm_selector_collect times each variant on
@@ -16,7 +16,15 @@ of the time.
 Training runs on the GPU (spmm_selector_train: minibatch Adam on the MSE).
 A held-out graph (seed 17) measures the result: per (k, type), the time the
 learned choice costs over the per-bucket optimum of the exhaustive timing
-(the regret), next to the regret of each fixed variant.
+(the regret), next to the regret of each fixed variant; and whole SpMM runs
+on it with each fixed variant, the autotuner and the learned choice.
+
+Bucket timings see each bucket alone, repeated to fill the GPU; inside a
+whole SpMM the variants' costs shift (other tiles share the caches and the
+memory system), so small predicted gains do not carry over.  The shipped
+weights therefore keep the build default (HYBRID) unless another variant is
+predicted at least --default-margin faster: that margin is folded into the
+output bias of HYBRID.
 
 Writes DIR/selector_weights.npy (float32[SPMM_MLP_PARAMS]) and
 DIR/selector_train.json (data, loss trace, held-out regrets).
@@ -41,7 +49,7 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_wei
 
 # (scale, edge factor, graph seed, symmetrise)
 TRAIN_GRAPHS = [(18, 16, 18, False), (19, 8, 19, True), (20, 16, 11, False), (21, 44, 12, False),
-                (22, 8, 13, True), (21, 28, 14, True), (22, 44, 15, False)]
+                (22, 8, 13, True), (21, 28, 14, True), (22, 44, 15, False), (24, 24, 21, False)]
 HELD_OUT = (22, 32, 17, False)
 QUICK_GRAPHS = [(16, 16, 11, False), (17, 8, 13, True)]
 QUICK_HELD_OUT = (17, 16, 17, False)
@@ -97,12 +105,65 @@ def regrets(h, params, k, dt, keep=None):
     return out
 
 
+B3_OFFSET = 8 * 64 + 64 + 64 * 64 + 64 + 64 * pk.SPMM_NUM_VARIANTS   # output-layer bias (spmm.h layout)
+FULL_KS = (1, 2, 4, 8, 16, 32)
+
+
+def full_runs(g, params, reps=20):
+    """Whole-SpMM times on graph g (ms, FP32 X) for each fixed variant, the
+    exhaustive autotuner and the learned choice, per k and summed."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    rp, col = graph(*g)
+    n = rp.shape[0] - 1
+    h = pk.spmm_build_tiles(rp, col, validate=False)
+    T = pk.spmm_get_stats(h)["n_tiles"]
+    pd = torch.from_numpy(params).to(dev)
+
+    def t(X, Y):
+        pk.spmm_run(h, X, Y)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            pk.spmm_run(h, X, Y)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    per_k = {}
+    for k in FULL_KS:
+        X = torch.from_numpy(synth.uniform(n, k, seed=2)).to(dev)
+        Y = torch.empty((n, k), device=dev)
+        row = {}
+        for v, name in enumerate(pk.VARIANT_NAMES):
+            pk.spmm_set_variants(h, np.full(T, v, np.uint8))
+            row[name] = t(X, Y)
+        pk.spmm_autotune(h, k)
+        row["autotune"] = t(X, Y)
+        f = torch.from_numpy(pk.spmm_tile_features(h, k)).to(dev)
+        ch = torch.empty(f.shape[0], dtype=torch.uint8, device=dev)
+        pk.spmm_mlp_predict(pd, f, None, ch)
+        torch.cuda.synchronize()
+        pk.spmm_set_variants(h, ch.cpu().numpy())
+        row["learned"] = t(X, Y)
+        per_k[str(k)] = {a: round(v, 4) for a, v in row.items()}
+    h.close()
+    names = list(per_k[str(FULL_KS[0])])
+    return {"graph": list(g), "per_k": per_k,
+            "sum_ms": {a: round(sum(per_k[str(k)][a] for k in FULL_KS), 4) for a in names}}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default=os.path.dirname(WEIGHTS))
     ap.add_argument("--quick", action="store_true", help="small graphs (a functional run)")
     ap.add_argument("--per-bucket", type=int, default=64)
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=1200)
+    ap.add_argument("--default-margin", type=float, default=0.1,
+                    help="keep the build default (HYBRID) unless another variant is predicted at least this "
+                         "much faster (folded into the output bias of the shipped weights)")
     ap.add_argument("--dump", action="store_true",
                     help="also write the training rows and held-out timing tables (.npz)")
     ap.add_argument("--seed", type=int, default=5)
@@ -143,13 +204,21 @@ def main(argv=None) -> int:
         held_res.append({"k": k, "x": DT_NAMES[dt], "regret": r})
         log(f"held-out k={k} {DT_NAMES[dt]}: " + ", ".join(f"{a}={v * 100:.1f}%" for a, v in r.items()))
     h.close()
+    # the shipped weights favour the default variant by the margin: a tile
+    # leaves HYBRID only where another variant is predicted >= (1 + margin)
+    # times faster
+    shipped = params.astype(np.float32).copy()
+    shipped[B3_OFFSET + pk.SPMM_VAR_HYBRID] -= np.float32(np.log1p(args.default_margin))
+    full = full_runs(held, shipped)
+    log("held-out full SpMM runs (ms, sum over k): " + ", ".join(f"{a}={v:.3f}" for a, v in full["sum_ms"].items()))
     os.makedirs(args.out, exist_ok=True)
-    np.save(os.path.join(args.out, "selector_weights.npy"), params.astype(np.float32))
+    np.save(os.path.join(args.out, "selector_weights.npy"), shipped)
     with open(os.path.join(args.out, "selector_train.json"), "w") as fh:
         json.dump({"graphs": [list(g) for g in graphs], "held_out": list(held), "runs": meta,
                    "rows": int(F.shape[0]), "epochs": args.epochs, "seed": args.seed,
                    "train_s": round(t_train, 2), "loss_trace": [float(x) for x in trace],
-                   "held_out_regret": held_res}, fh, indent=1)
+                   "held_out_regret": held_res, "default_margin": args.default_margin,
+                   "held_out_full_runs": full}, fh, indent=1)
     if args.dump:
         np.savez_compressed(os.path.join(args.out, "selector_rows.npz"), feat=F, target=Y)
         np.savez_compressed(os.path.join(args.out, "selector_heldout.npz"),
