@@ -367,6 +367,13 @@ def main() -> int:
             lambda k=k: pk.spmm_run(hv, Xs[k], Ys[k], stream=stream)), 4) for k in ks}
         log(f"V-csr: {compare['v_csr']}")
         hv.close()
+        # the same CSR kernels over the original column order: the first step
+        # of the optimisation ladder (rows balanced by length, no locality)
+        hv = pk.spmm_build_tiles(rp, col, validate=False, format=pk.SPMM_FORMAT_CSR, keep_order=True)
+        compare["ablation_v_csr_original_columns"] = {str(k): round(time_one(
+            lambda k=k: pk.spmm_run(hv, Xs[k], Ys[k], stream=stream)), 4) for k in ks}
+        log(f"V-csr, original column order: {compare['ablation_v_csr_original_columns']}")
+        hv.close()
         # ablations: tiles over the original row order, and over the original
         # row and column order (no relabelling at all)
         for name, opt in (("ablation_original_row_order", dict(keep_row_order=True)),

@@ -2,8 +2,8 @@
 
     python -m paper_1602_02864_amd.selector_train [--out DIR] [--quick]
 
-Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 18-24 with graph
-seeds 11-15, 18, 19 and 21, directed and symmetrised, edge factors 8-44 --
+Data: R-MAT graphs (a/b/c/d = .57/.19/.19/.05) at scales 18-25 with graph
+seeds 11-15, 18, 19, 21 and 23, directed and symmetrised, edge factors 8-44 --
 never seed 1 (the benchmark graphs) or 17 (the held-out graphs).  Each graph is tiled with the library's
 default geometry (32-row tile rows, 65536-column strips).  For every graph,
 column count k and X type, spmm_selector_collect times each variant on
@@ -21,10 +21,13 @@ on it with each fixed variant, the autotuner and the learned choice.
 
 Bucket timings see each bucket alone, repeated to fill the GPU; inside a
 whole SpMM the variants' costs shift (other tiles share the caches and the
-memory system), so small predicted gains do not carry over.  The shipped
-weights therefore keep the build default (HYBRID) unless another variant is
-predicted at least --default-margin faster: that margin is folded into the
-output bias of HYBRID.
+memory system).  Two corrections follow.  Calibration: for every graph and
+setting, each fixed variant's whole SpMM is timed, and that variant's
+bucket times are scaled by one factor so that they sum to the measured
+time (the labels keep each bucket's relative cost within the variant).
+Margin: the shipped weights keep the build default (HYBRID) unless another
+variant is predicted at least --default-margin faster; the margin is
+folded into the output bias of HYBRID.
 
 Writes DIR/selector_weights.npy (float32[SPMM_MLP_PARAMS]) and
 DIR/selector_train.json (data, loss trace, held-out regrets).
@@ -49,7 +52,8 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_wei
 
 # (scale, edge factor, graph seed, symmetrise)
 TRAIN_GRAPHS = [(18, 16, 18, False), (19, 8, 19, True), (20, 16, 11, False), (21, 44, 12, False),
-                (22, 8, 13, True), (21, 28, 14, True), (22, 44, 15, False), (24, 24, 21, False)]
+                (22, 8, 13, True), (21, 28, 14, True), (22, 44, 15, False), (24, 24, 21, False),
+                (25, 44, 23, False)]
 HELD_OUT = (22, 32, 17, False)
 QUICK_GRAPHS = [(16, 16, 11, False), (17, 8, 13, True)]
 QUICK_HELD_OUT = (17, 16, 17, False)
@@ -69,7 +73,8 @@ def graph(scale, ef, seed, sym):
 
 
 def collect_rows(h, k, dt, per_bucket, rng):
-    """Feature rows and log-ns labels of (at most per_bucket) tiles per bucket."""
+    """Features of (at most per_bucket) tiles per bucket, with their buckets'
+    ns per tile for every variant."""
     b, ns = pk.spmm_selector_collect(h, k, dt)
     f = pk.spmm_tile_features(h, k, dt)
     keep = []
@@ -79,8 +84,69 @@ def collect_rows(h, k, dt, per_bucket, rng):
             idx = rng.choice(idx, per_bucket, replace=False)
         keep.append(idx)
     keep = np.concatenate(keep) if keep else np.zeros(0, np.int64)
-    y = np.log(np.maximum(ns[b[keep]], 1e-3)).astype(np.float32)
-    return f[keep], y, b, ns
+    return f[keep], ns[b[keep]], b, ns
+
+
+def _x_input(X, dt):
+    """X (device FP32) in the X type dt: the tensor and its column scales."""
+    import torch
+    if dt == pk.SPMM_X_F32:
+        return X, None
+    if dt == pk.SPMM_X_BF16:
+        Xq = torch.empty(X.shape, dtype=torch.bfloat16, device=X.device)
+        pk.spmm_quantize_x(X, Xq, dt)
+        return Xq, None
+    Xq = torch.empty(X.shape, dtype=torch.uint8, device=X.device)
+    cs = torch.empty(X.shape[1], dtype=torch.float32, device=X.device)
+    pk.spmm_quantize_x(X, Xq, dt, col_scale=cs)
+    return Xq, cs
+
+
+def _timed(h, X, Y, dt, cs, reps):
+    """Mean ms of one SpMM over reps launches after a warm-up."""
+    import torch
+    pk.spmm_run(h, X, Y, dtype=dt, col_scale=cs)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        pk.spmm_run(h, X, Y, dtype=dt, col_scale=cs)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def whole_times(h, settings, reps=10):
+    """ms of a whole SpMM with every tile in variant v, for each (k, X type)
+    setting and variant: float64[len(settings), V].  The handle's variants
+    are left as HYBRID."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    st = pk.spmm_get_stats(h)
+    T, n, m = st["n_tiles"], st["n_rows"], st["n_cols"]
+    xs = {}
+    for k, dt in settings:
+        if k not in xs:
+            xs[k] = torch.from_numpy(synth.uniform(m, k, seed=2)).to(dev)
+    out = np.zeros((len(settings), pk.SPMM_NUM_VARIANTS))
+    for v in range(pk.SPMM_NUM_VARIANTS):
+        pk.spmm_set_variants(h, np.full(T, v, np.uint8))
+        for i, (k, dt) in enumerate(settings):
+            Xin, cs = _x_input(xs[k], dt)
+            Y = torch.empty((n, k), device=dev)
+            out[i, v] = _timed(h, Xin, Y, dt, cs, reps)
+            del Xin, Y
+    pk.spmm_set_variants(h, np.full(T, pk.SPMM_VAR_HYBRID, np.uint8))
+    return out
+
+
+def calibration(b, ns, whole_ms):
+    """Per-variant factor that scales the bucket times of one (graph,
+    setting) to the variant's measured whole-SpMM time: the summed bucket
+    time of every tile in variant v is sum_t ns[b[t], v]."""
+    pred_ns = ns[b].sum(axis=0).astype(np.float64)
+    return whole_ms * 1e6 / np.maximum(pred_ns, 1e-9)
 
 
 def regrets(h, params, k, dt, keep=None):
@@ -164,6 +230,8 @@ def main(argv=None) -> int:
     ap.add_argument("--default-margin", type=float, default=0.1,
                     help="keep the build default (HYBRID) unless another variant is predicted at least this "
                          "much faster (folded into the output bias of the shipped weights)")
+    ap.add_argument("--no-calibrate", dest="calibrate", action="store_false",
+                    help="train on the raw bucket timings (no scaling to whole-SpMM times)")
     ap.add_argument("--dump", action="store_true",
                     help="also write the training rows and held-out timing tables (.npz)")
     ap.add_argument("--seed", type=int, default=5)
@@ -179,13 +247,25 @@ def main(argv=None) -> int:
         rp, col = graph(*g)
         h = pk.spmm_build_tiles(rp, col, validate=False)
         T = pk.spmm_get_stats(h)["n_tiles"]
+        got = []
         for k, dt in RUNS:
-            f, y, b, ns = collect_rows(h, k, dt, args.per_bucket, rng)
-            F.append(f)
-            Y.append(y)
-            meta.append({"graph": g, "k": k, "x": DT_NAMES[dt], "tiles": T, "buckets": int(ns.shape[0]),
-                         "rows": int(f.shape[0])})
+            f, nsr, b, ns = collect_rows(h, k, dt, args.per_bucket, rng)
+            got.append((f, nsr, b, ns))
             log(f"graph {g} k={k} {DT_NAMES[dt]}: {ns.shape[0]} buckets, {f.shape[0]} rows")
+        # in-context calibration: each variant's bucket times of this graph
+        # and setting are scaled to sum to its measured whole-SpMM time
+        whole = whole_times(h, RUNS) if args.calibrate else None
+        for i, ((k, dt), (f, nsr, b, ns)) in enumerate(zip(RUNS, got)):
+            c = calibration(b, ns, whole[i]) if whole is not None else np.ones(pk.SPMM_NUM_VARIANTS)
+            F.append(f)
+            Y.append(np.log(np.maximum(nsr * c[None, :], 1e-3)).astype(np.float32))
+            meta.append({"graph": g, "k": k, "x": DT_NAMES[dt], "tiles": T, "buckets": int(ns.shape[0]),
+                         "rows": int(f.shape[0]), "whole_ms": None if whole is None else [round(x, 4) for x in whole[i]],
+                         "calibration": [round(float(x), 4) for x in c]})
+            if whole is not None:
+                log(f"graph {g} k={k} {DT_NAMES[dt]}: whole ms " + ", ".join(
+                    f"{nm}={t:.3f}" for nm, t in zip(pk.VARIANT_NAMES, whole[i])) +
+                    "; calibration " + ", ".join(f"{x:.3f}" for x in c))
         h.close()
         log(f"graph {g} done in {time.perf_counter() - t0:.1f}s")
     F = np.concatenate(F)
@@ -218,6 +298,7 @@ def main(argv=None) -> int:
                    "rows": int(F.shape[0]), "epochs": args.epochs, "seed": args.seed,
                    "train_s": round(t_train, 2), "loss_trace": [float(x) for x in trace],
                    "held_out_regret": held_res, "default_margin": args.default_margin,
+                   "calibrated": bool(args.calibrate),
                    "held_out_full_runs": full}, fh, indent=1)
     if args.dump:
         np.savez_compressed(os.path.join(args.out, "selector_rows.npz"), feat=F, target=Y)
