@@ -26,8 +26,10 @@ setting, each fixed variant's whole SpMM is timed, and that variant's
 bucket times are scaled by one factor so that they sum to the measured
 time (the labels keep each bucket's relative cost within the variant).
 Margin: the shipped weights keep the build default (HYBRID) unless another
-variant is predicted at least --default-margin faster; the margin is
-folded into the output bias of HYBRID.
+variant is predicted at least a margin faster (folded into the output bias
+of HYBRID); of the candidate --margins, the one whose learned choice gives
+the fastest whole SpMMs (summed over k = 1..32) on the largest training
+graph is shipped.
 
 Writes DIR/selector_weights.npy (float32[SPMM_MLP_PARAMS]) and
 DIR/selector_train.json (data, loss trace, held-out regrets).
@@ -175,6 +177,40 @@ B3_OFFSET = 8 * 64 + 64 + 64 * 64 + 64 + 64 * pk.SPMM_NUM_VARIANTS   # output-la
 FULL_KS = (1, 2, 4, 8, 16, 32)
 
 
+def with_margin(params, margin):
+    """The weights with HYBRID favoured by the margin: a tile leaves HYBRID
+    only where another variant is predicted >= (1 + margin) times faster."""
+    p = params.astype(np.float32).copy()
+    p[B3_OFFSET + pk.SPMM_VAR_HYBRID] -= np.float32(np.log1p(margin))
+    return p
+
+
+def margin_sweep(h, params, margins, reps=10):
+    """Whole-SpMM ms summed over FULL_KS (FP32 X) on handle h: every tile
+    HYBRID, and the learned choice at each margin."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    st = pk.spmm_get_stats(h)
+    T, n, m = st["n_tiles"], st["n_rows"], st["n_cols"]
+    xs = {k: torch.from_numpy(synth.uniform(m, k, seed=2)).to(dev) for k in FULL_KS}
+    ys = {k: torch.empty((n, k), device=dev) for k in FULL_KS}
+    tot = {"hybrid": 0.0, **{str(mg): 0.0 for mg in margins}}
+    pk.spmm_set_variants(h, np.full(T, pk.SPMM_VAR_HYBRID, np.uint8))
+    for k in FULL_KS:
+        tot["hybrid"] += _timed(h, xs[k], ys[k], pk.SPMM_X_F32, None, reps)
+    ch = torch.empty(T, dtype=torch.uint8, device=dev)
+    for k in FULL_KS:
+        f = torch.from_numpy(pk.spmm_tile_features(h, k)).to(dev)
+        for mg in margins:
+            pk.spmm_mlp_predict(torch.from_numpy(with_margin(params, mg)).to(dev), f, None, ch)
+            torch.cuda.synchronize()
+            pk.spmm_set_variants(h, ch.cpu().numpy())
+            tot[str(mg)] += _timed(h, xs[k], ys[k], pk.SPMM_X_F32, None, reps)
+        del f
+    return {a: round(v, 4) for a, v in tot.items()}
+
+
 def full_runs(g, params, reps=20):
     """Whole-SpMM times on graph g (ms, FP32 X) for each fixed variant, the
     exhaustive autotuner and the learned choice, per k and summed."""
@@ -227,9 +263,10 @@ def main(argv=None) -> int:
     ap.add_argument("--quick", action="store_true", help="small graphs (a functional run)")
     ap.add_argument("--per-bucket", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=1200)
-    ap.add_argument("--default-margin", type=float, default=0.1,
-                    help="keep the build default (HYBRID) unless another variant is predicted at least this "
-                         "much faster (folded into the output bias of the shipped weights)")
+    ap.add_argument("--margins", default="0.05,0.1,0.2,0.3",
+                    help="candidate margins: keep the build default (HYBRID) unless another variant is predicted "
+                         "at least this much faster (folded into the output bias of the shipped weights); with "
+                         "several, the one with the fastest whole SpMMs on the largest training graph is shipped")
     ap.add_argument("--no-calibrate", dest="calibrate", action="store_false",
                     help="train on the raw bucket timings (no scaling to whole-SpMM times)")
     ap.add_argument("--dump", action="store_true",
@@ -266,7 +303,10 @@ def main(argv=None) -> int:
                 log(f"graph {g} k={k} {DT_NAMES[dt]}: whole ms " + ", ".join(
                     f"{nm}={t:.3f}" for nm, t in zip(pk.VARIANT_NAMES, whole[i])) +
                     "; calibration " + ", ".join(f"{x:.3f}" for x in c))
-        h.close()
+        if g == graphs[-1]:
+            h_last = h          # the largest training graph: kept for the margin choice
+        else:
+            h.close()
         log(f"graph {g} done in {time.perf_counter() - t0:.1f}s")
     F = np.concatenate(F)
     Y = np.concatenate(Y)
@@ -284,11 +324,18 @@ def main(argv=None) -> int:
         held_res.append({"k": k, "x": DT_NAMES[dt], "regret": r})
         log(f"held-out k={k} {DT_NAMES[dt]}: " + ", ".join(f"{a}={v * 100:.1f}%" for a, v in r.items()))
     h.close()
-    # the shipped weights favour the default variant by the margin: a tile
-    # leaves HYBRID only where another variant is predicted >= (1 + margin)
-    # times faster
-    shipped = params.astype(np.float32).copy()
-    shipped[B3_OFFSET + pk.SPMM_VAR_HYBRID] -= np.float32(np.log1p(args.default_margin))
+    # the margin: chosen by whole SpMM runs on the largest training graph
+    margins = [float(x) for x in args.margins.split(",") if x.strip()]
+    sweep = None
+    if len(margins) > 1:
+        sweep = margin_sweep(h_last, params, margins)
+        margin = min(margins, key=lambda mg: (sweep[str(mg)], -mg))
+        log(f"margin sweep on {graphs[-1]} (ms, sum over k): " + ", ".join(f"{a}={v:.3f}" for a, v in sweep.items()) +
+            f" -> margin {margin}")
+    else:
+        margin = margins[0] if margins else 0.0
+    h_last.close()
+    shipped = with_margin(params, margin)
     full = full_runs(held, shipped)
     log("held-out full SpMM runs (ms, sum over k): " + ", ".join(f"{a}={v:.3f}" for a, v in full["sum_ms"].items()))
     os.makedirs(args.out, exist_ok=True)
@@ -297,7 +344,7 @@ def main(argv=None) -> int:
         json.dump({"graphs": [list(g) for g in graphs], "held_out": list(held), "runs": meta,
                    "rows": int(F.shape[0]), "epochs": args.epochs, "seed": args.seed,
                    "train_s": round(t_train, 2), "loss_trace": [float(x) for x in trace],
-                   "held_out_regret": held_res, "default_margin": args.default_margin,
+                   "held_out_regret": held_res, "default_margin": margin, "margin_sweep": sweep,
                    "calibrated": bool(args.calibrate),
                    "held_out_full_runs": full}, fh, indent=1)
     if args.dump:

@@ -118,3 +118,22 @@ def test_selection_argument_errors():
     assert ei.value.status == pk.SPMM_EINVAL
     hd.close()
     hp.close()
+
+
+def test_training_calibration_and_margin():
+    """The training script's host arithmetic: calibrated bucket times of
+    each variant sum to its whole-SpMM time, and the margin moves only
+    HYBRID's output bias, by -log(1 + margin)."""
+    from paper_1602_02864_amd.selector_train import B3_OFFSET, calibration, with_margin
+    rng = np.random.default_rng(3)
+    b = rng.integers(0, 5, 1000)
+    ns = rng.uniform(10.0, 500.0, (5, pk.SPMM_NUM_VARIANTS))
+    whole = np.array([3.0, 5.0, 2.5, 9.0])
+    c = calibration(b, ns, whole)
+    assert np.allclose((ns[b] * c[None, :]).sum(axis=0) * 1e-6, whole, rtol=1e-12)
+    assert B3_OFFSET == pk.SPMM_MLP_OFF_B3
+    p = pk.spmm_mlp_init(11)
+    q = with_margin(p, 0.2)
+    d = np.flatnonzero(q != p)
+    assert list(d) == [pk.SPMM_MLP_OFF_B3 + pk.SPMM_VAR_HYBRID]
+    assert np.isclose(q[d[0]] - p[d[0]], -np.log1p(0.2), rtol=1e-6)
