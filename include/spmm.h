@@ -227,6 +227,11 @@ const char* spmm_last_error(void);
  *   s     : HIP stream (0 = null stream).
  * The first call on a handle copies the tile payload to HBM and allocates
  * the partial-result buffer of split tile rows (synchronous allocations).
+ * Rows without entries of a handle that orders rows by degree are not
+ * tiled and are zero-filled: when there are at least 2^26 such values and s
+ * is not being captured, on a stream the handle owns, forked from s at the
+ * start of the call and joined back into s before it returns (so all of
+ * the call's work stays ordered on s).
  *
  * Arithmetic.  X is decoded to FP32 and multiplied by A's value in FP32.
  * The products are summed exactly, in 64-bit fixed point: column j uses the

@@ -98,7 +98,11 @@ struct Solver {
     hipStream_t copy = nullptr;  // tiles in host memory: the stream of the tile copies
     int64_t n;
     int b, m;
-    spmm::ColLayout VL;   // the basis: blocks of b columns, each n x b contiguous
+    // The basis: for b >= 4, blocks of b columns, each n x b contiguous; for
+    // narrower blocks row-major with m + b columns (contiguous blocks of one
+    // or two columns would make the basis kernels read one float per line
+    // per lane).  Block c / b starts at col_off(VL, c), row stride VL.ld.
+    spmm::ColLayout VL;
     float* V[2];
     float* W;
     float* Z;    // n x b scratch block
@@ -172,13 +176,14 @@ struct Solver {
         return e == hipSuccess ? SPMM_OK : hip_fail(e, "random fill launch");
     }
 
-    // Y = A X for a block of b basis columns, timed with events.
+    // Y (n x b, stride b) = A X for a block of b basis columns (stride
+    // VL.ld), timed with events.
     spmm_status_t product(const float* X, float* Y) {
         hipError_t e;
         if ((e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         spmm_status_t st = H.place == SPMM_PLACE_DEVICE
-                               ? spmm_abi::run_device(H, X, b, b, SPMM_X_F32, nullptr, Y, b, s, false)
-                               : spmm_stream_run(h, X, b, b, SPMM_X_F32, nullptr, Y, b, s, copy);
+                               ? spmm_abi::run_device(H, X, b, VL.ld, SPMM_X_F32, nullptr, Y, b, s, false)
+                               : spmm_stream_run(h, X, b, VL.ld, SPMM_X_F32, nullptr, Y, b, s, copy);
         if (st != SPMM_OK) return st;
         if ((e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         if ((e = hipEventSynchronize(ev1)) != hipSuccess) return hip_fail(e, "SpMM");
@@ -257,7 +262,8 @@ struct Solver {
     }
 
     // Make the block W (n x b, stride b) orthogonal to the first nb columns
-    // of Vc and orthonormal, writing it to the basis block Dst: W ~ Dst R.  coef
+    // of Vc and orthonormal, writing it to the basis block Dst (stride
+    // VL.ld): W ~ Dst R.  coef
     // receives Vb^T W (nb x b), R (b x b) is Dst^T W after the projection
     // (from the two Gram matrices when W has full rank).  Directions of W
     // lost to cancellation are replaced by random vectors orthogonal to the
@@ -323,12 +329,13 @@ struct Solver {
             std::vector<double> unused;
             double unused2;
             if (nb > 0 && (st = project_out(Vc, nb, Z, b, b, unused, unused2)) != SPMM_OK) return st;
-            if ((st = svqb(Z, b, Dst, b)) != SPMM_OK) return st;
-            hipError_t e = hipMemcpyAsync(Z, Dst, (size_t)n * b * sizeof(float), hipMemcpyDeviceToDevice, s);
+            if ((st = svqb(Z, b, Dst, VL.ld)) != SPMM_OK) return st;
+            hipError_t e = hipMemcpy2DAsync(Z, (size_t)b * sizeof(float), Dst, (size_t)VL.ld * sizeof(float),
+                                            (size_t)b * sizeof(float), (size_t)n, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return hip_fail(e, "basis block copy");
         }
         // second pass for orthogonality within the block
-        if ((st = svqb(Z, b, Dst, b, {}, {}, &s2)) != SPMM_OK) return st;
+        if ((st = svqb(Z, b, Dst, VL.ld, {}, {}, &s2)) != SPMM_OK) return st;
         R.resize((size_t)b * b);
         if (r == b) {
             // W = Z G1^{1/2} and Z = Dst G2^{1/2}, so R = G2^{1/2} G1^{1/2}:
@@ -341,7 +348,7 @@ struct Solver {
                 }
             return SPMM_OK;
         }
-        if ((st = tn(Dst, spmm::row_major(b), b, W, b, b, dC)) != SPMM_OK) return st;
+        if ((st = tn(Dst, spmm::row_major(VL.ld), b, W, b, b, dC)) != SPMM_OK) return st;
         if ((st = get(R.data(), dC, R.size())) != SPMM_OK) return st;
         return sync("block orthonormalisation");
     }
@@ -448,7 +455,7 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
         }
 
         spmm_abi::DevBufs bufs;
-        Solver S{h, H, s, own.copy, n, b, m, spmm::ColLayout{b, b, n * b}};
+        Solver S{h, H, s, own.copy, n, b, m, b >= 4 ? spmm::ColLayout{b, b, n * b} : spmm::row_major(m + b)};
         S.V[0] = bufs.get<float>((size_t)n * (m + b));
         S.V[1] = bufs.get<float>((size_t)n * (m + b));
         S.W = bufs.get<float>((size_t)n * b);
@@ -488,9 +495,9 @@ extern "C" spmm_status_t spmm_eigs(spmm_handle_t h, const spmm_eigs_opts* o, dou
             // expand the basis to m columns, one block at a time
             while (cur < m) {
                 const int nb = cur + b;
-                // basis column c starts block c / b, at Vc + c n (c a multiple of b)
-                if ((st = S.product(Vc + (size_t)cur * n, S.W)) != SPMM_OK) return st;
-                if ((st = S.orthonormalise(Vc, nb, Vc + (size_t)nb * n, coef, R)) != SPMM_OK) return st;
+                // the block of basis columns cur .. cur + b - 1 starts at col_off(VL, cur)
+                if ((st = S.product(Vc + spmm::col_off(S.VL, cur), S.W)) != SPMM_OK) return st;
+                if ((st = S.orthonormalise(Vc, nb, Vc + spmm::col_off(S.VL, nb), coef, R)) != SPMM_OK) return st;
                 for (int r = 0; r < nb; ++r)
                     for (int x = 0; x < b; ++x) {
                         const double v = coef[(size_t)r * b + x];

@@ -209,6 +209,10 @@ struct Handle {
     uint64_t yslot_bytes = 0;
     std::vector<hipEvent_t> ev_y_ready, ev_y_free;
     std::vector<uint8_t> y_used;     // slot's copy-out has been enqueued (ev_y_free recorded)
+    // side stream that zero-fills the rows without entries while the SpMM
+    // runs (fork and join events on the caller's stream)
+    hipStream_t zstream = nullptr;
+    hipEvent_t ev_zfork = nullptr, ev_zjoin = nullptr;
     int device = 0;
     bool uploaded = false;
     // optional timing of the SpMM launches of each run (event pairs)
