@@ -272,6 +272,8 @@ spmm_status_t zero_empty_rows(const spmm::Handle& H, float* Y, int64_t ldy, int 
 // Below 2^26 values (256 MB) the fill is shorter than what the fork, the
 // join and the fill's share of the CUs cost the SpMM (measured at scale 25:
 // slower by 0.1-0.2 ms for k <= 4, faster by 0.4-0.7 ms for k >= 16).
+// Zero-fill wavefronts inside the SpMM launch were measured too: after the
+// last item they gained less, spread among the items they slowed it.
 constexpr int64_t kZeroSideMin = int64_t(1) << 26;   // zero-filled values
 
 bool fork_zero_rows(spmm::Handle& H, float* Y, int64_t ldy, int k, hipStream_t s) {
