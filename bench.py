@@ -104,7 +104,7 @@ def time_step(runs, steps, warmup, stream):
 
 def attainable_read_gbs(gib=16, reps=5):
     """Read rate of a plain streaming-read kernel over gib GiB (the HBM rate a
-    simple kernel attains on this machine, beside the 8 TB/s nominal)."""
+    simple kernel attains on this GPU, beside the 8 TB/s nominal)."""
     import torch
 
     import paper_1602_02864_amd as pk
@@ -176,7 +176,7 @@ def main() -> int:
         return run_other_modes(args, modes)
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         return 2
 

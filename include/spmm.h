@@ -40,7 +40,7 @@ typedef enum {
     SPMM_EINVAL = -1,        /* bad argument or malformed CSR                 */
     SPMM_ENOMEM = -2,        /* host or device allocation failed              */
     SPMM_EHIP = -3,          /* a HIP runtime call failed                     */
-    SPMM_EUNSUPPORTED = -4,  /* valid request this build does not support     */
+    SPMM_EUNSUPPORTED = -4,  /* valid request this library does not support   */
     SPMM_ESTATE = -5,        /* handle is in the wrong state for this call    */
     SPMM_ENOTCONV = -6       /* an iterative method stopped before converging */
 } spmm_status_t;
