@@ -46,3 +46,13 @@ def test_sample_rows_cover_hubs_and_spread_blocks():
     assert 0.5 * 200_000 <= nnz - 64 * 8 <= 2 * 200_000
     # blocks spread over the whole range
     assert sel[-1] > 0.9 * n
+
+
+def test_traffic_reported_only_for_the_profiled_kernel(monkeypatch):
+    """The committed counter summary prices the dominant launch only while
+    it was taken on this kernel source and column chunk."""
+    got = bench.measured_traffic(32)
+    assert got is not None and got > 0
+    assert bench.measured_traffic(16) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic(32) is None
