@@ -51,8 +51,16 @@ def test_sample_rows_cover_hubs_and_spread_blocks():
 def test_traffic_reported_only_for_the_profiled_kernel(monkeypatch):
     """The committed counter summary prices the dominant launch only while
     it was taken on this kernel source and column chunk."""
-    got = bench.measured_traffic(32)
-    assert got is not None and got > 0
-    assert bench.measured_traffic(16) is None
+    recorded = {}
+    for line in open(bench.TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            a, b = line.split("=", 1)
+            recorded[a.strip()] = b.strip()
+    got = bench.measured_traffic(int(recorded["kc"]))
+    if recorded["kernel_source_sha256_16"] == bench.kernel_source_hash():
+        assert got == int(recorded["hbm_bytes_per_launch"])
+    else:
+        assert got is None
+    assert bench.measured_traffic(int(recorded["kc"]) // 2) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic(32) is None
+    assert bench.measured_traffic(int(recorded["kc"])) is None
